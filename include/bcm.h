@@ -1,0 +1,224 @@
+/*
+ * bcm.h -- C ABI of the building-cube projection library for MI355X (gfx950).
+ *
+ * The library implements the projection part of the paper's fractional-step method
+ * (Sec. 3: immersed-body forcing, pressure Poisson equation, velocity correction) on a
+ * building-cube mesh (Sec. 2.2: cubes of equal cell count n^3, 2:1 size ratio between
+ * face neighbours, a neighbour adjacency table instead of a tree).  The Poisson equation
+ * is solved by geometric multigrid coarsened inside each cube, with a conjugate-gradient
+ * solve on the one-cell-per-cube level (Sec. 3 and Sec. 7: at most 10 coarse CG
+ * iterations, at most 50 V-cycles), here wrapped in flexible CG and, in the mixed modes,
+ * in FP64 iterative refinement.
+ *
+ * Conventions shared by every call:
+ *   - All field pointers are DEVICE pointers owned by the caller.  Scalar fields are
+ *     stored cube-major, [cube][k][j][i] with i fastest, n^3 values per cube, in the
+ *     cube order of the mesh description.  Vector fields are passed as three separate
+ *     component arrays.
+ *   - Field element type: FP64 ("double") in BCM_FP64 and BCM_MIXED; FP32 ("float") for
+ *     u, alpha, u_s, u_new, face_u and the velocity cotangents in BCM_MIXED_F32FIELDS.
+ *     Pressure, the adjoint pressure and g_p are always FP64.
+ *   - The library never allocates device memory: bcm_plan_create reports the workspace
+ *     size and the caller binds a buffer of at least that size (bcm_plan_bind).
+ *   - All GPU work is enqueued on the caller's stream (a hipStream_t passed as void*;
+ *     NULL = the default stream).  Calls that return solver results synchronise that
+ *     stream at convergence checks; the others are asynchronous.
+ *   - Return value: BCM_OK (0), a positive warning (outputs valid) or a negative error
+ *     (outputs unspecified).  bcm_last_error() returns a thread-local description of the
+ *     last error of the calling thread.  No C++ exception crosses this boundary.
+ *   - Calls on the same plan must not overlap (they share its workspace).
+ */
+#ifndef BCM_H
+#define BCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bcm_mesh bcm_mesh;
+typedef struct bcm_plan bcm_plan;
+
+enum {
+  BCM_OK = 0,
+  BCM_NOT_CONVERGED = 1,       /* tolerance not reached within the iteration limits */
+  BCM_ERR_INVALID_ARG = -1,
+  BCM_ERR_INVALID_MESH = -2,
+  BCM_ERR_WORKSPACE = -3,      /* no workspace bound, or the bound one is too small */
+  BCM_ERR_NONFINITE = -4,      /* a residual norm became NaN or Inf */
+  BCM_ERR_HIP = -5,            /* a HIP runtime call failed (text in bcm_last_error) */
+  BCM_ERR_UNSUPPORTED = -6
+};
+
+/* Boundary kind of a cube face on the domain boundary (face_bc). */
+enum {
+  BCM_BC_NONE = 0,     /* interior face (has a neighbour) */
+  BCM_BC_OUTFLOW = 1,  /* open: p = 0 on the face, face velocity = boundary-cell velocity */
+  BCM_BC_INFLOW = 2,   /* normal velocity U_in into the domain, dp/dn = 0, never corrected */
+  BCM_BC_SLIP = 3      /* zero normal velocity, dp/dn = 0 */
+};
+
+/* Precision modes. */
+enum {
+  BCM_FP64 = 0,             /* everything in FP64 (flexible CG + V-cycle in FP64) */
+  BCM_MIXED = 1,            /* FP64 fields, residual and refinement; FP32 sweeps and preconditioner */
+  BCM_MIXED_F32FIELDS = 2   /* as BCM_MIXED with FP32 velocity / volume-fraction fields */
+};
+
+/*
+ * Mesh description (host memory, copied by bcm_mesh_create).  The paper's linear-array
+ * mesh (Sec. 2.2): base corner, size (level), cell count and neighbour adjacency.
+ *   n          cells per cube edge: 2, 4, 8 or 16
+ *   origin     [n_cubes][3] base (minimum) corner of each cube
+ *   level      [n_cubes] refinement level, 0 = coarsest; cube edge = root_edge / 2^level
+ *   nbr        [n_cubes][6][4] neighbours across faces (-x,+x,-y,+y,-z,+z):
+ *                same-level or coarser neighbour: slot 0 = its index, slots 1..3 = -1;
+ *                finer neighbours (2:1): the 4 cubes covering the face, slot a + 2b where
+ *                a (b) is the lower/upper half along the first (second) tangential axis,
+ *                tangential axes in increasing order (x-face: y,z; y-face: x,z; z-face: x,y);
+ *                domain boundary: all four slots -1.
+ *   face_bc    [n_cubes][6] BCM_BC_* of boundary faces, BCM_BC_NONE on interior faces.
+ * Requirements checked by bcm_mesh_create: neighbour links are reciprocal and agree with
+ * the geometry, face neighbours differ by at most one level, every boundary face has a
+ * kind, and at least one face is BCM_BC_OUTFLOW (so the Poisson problem is nonsingular).
+ */
+typedef struct {
+  int32_t n_cubes;
+  int32_t n;
+  const double* origin;
+  const int8_t* level;
+  double root_edge;
+  const int32_t* nbr;
+  const int8_t* face_bc;
+} bcm_mesh_desc;
+
+/* Solver options; bcm_default_opts fills the defaults given in brackets. */
+typedef struct {
+  int32_t precision;    /* BCM_FP64 / BCM_MIXED / BCM_MIXED_F32FIELDS            [BCM_FP64] */
+  double tol;           /* target ||b - A p||_V / ||b||_V, evaluated in FP64       [1e-10] */
+  int32_t max_iter;     /* Krylov iterations per solve (FP64 mode) / per inner solve   [50] */
+  int32_t max_outer;    /* mixed modes: FP64 refinement steps                          [10] */
+  double inner_tol;     /* mixed modes: relative tolerance of each FP32 inner solve  [1e-5] */
+  int32_t pre_sweeps;   /* red-black Gauss-Seidel sweeps before restriction             [2] */
+  int32_t post_sweeps;  /* sweeps after prolongation                                    [2] */
+  int32_t coarse_iters; /* CG iterations on the one-cell-per-cube level                 [10] */
+  int32_t krylov;       /* 1 = flexible CG preconditioned by one V-cycle, 0 = V-cycles  [1] */
+} bcm_solver_opts;
+
+/* Per-call solver report (host memory). */
+typedef struct {
+  int32_t status;        /* same value as the call's return code */
+  int32_t n_outer;       /* refinement steps (mixed) or 1 (FP64) */
+  int32_t n_inner;       /* total Krylov (or V-cycle) iterations */
+  double final_rel_res;  /* true FP64 relative residual of the returned pressure */
+  double* history;       /* caller array of history_cap doubles, or NULL: relative residual
+                            after every iteration (inner ones rescaled to the FP64 RHS) */
+  int32_t history_cap;
+  int32_t history_len;   /* entries written */
+} bcm_report;
+
+/* Inputs of one projection step (Sec. 3): u* = (1 - alpha) u~ + alpha u_s; Poisson; correction. */
+typedef struct {
+  const void* u[3];      /* intermediate velocity u~ (device fields) */
+  const void* alpha;     /* solid volume fraction in [0, 1] (device field), NULL = no body */
+  const void* us[3];     /* body velocity fields, or all NULL to use us_const */
+  double us_const[3];
+  double U_in;           /* inflow speed on BCM_BC_INFLOW faces */
+  double dt, rho;        /* time step and density (dt/rho scales the correction) */
+  const double* p0;      /* initial pressure guess (device, FP64) or NULL (zero) */
+} bcm_project_in;
+
+typedef struct {
+  void* u_new[3];        /* corrected cell velocity u^{n+1} (device fields) */
+  double* p;             /* pressure p^{n+1} (device, FP64, n_cubes * n^3) */
+  void* face_u[3];       /* optional corrected face-normal velocities, or NULL each:
+                            face_u[d] is [cube][k][j][i] with n+1 entries along axis d
+                            (x: [n][n][n+1], y: [n][n+1][n], z: [n+1][n][n]) */
+} bcm_project_out;
+
+/* Inputs of the adjoint of one projection step (same forward inputs, no pressure needed:
+ * the step is affine in u~ and polynomial in alpha). */
+typedef struct {
+  const void* u[3];
+  const void* alpha;     /* NULL = no body (then g_alpha is not written) */
+  const void* us[3];
+  double us_const[3];
+  double U_in, dt, rho;
+  const void* g_u_new[3];  /* cotangent of u^{n+1} (device fields) */
+  const double* g_p;       /* cotangent of p^{n+1} (device, FP64) or NULL */
+} bcm_adjoint_in;
+
+typedef struct {
+  void* g_u[3];          /* cotangent of u~ (written) */
+  void* g_alpha;         /* cotangent of alpha (written; ignored when alpha is NULL) */
+  double g_U_in;         /* cotangent of U_in (host scalar, written) */
+  double* lambda;        /* optional: adjoint pressure A^{-T}(...) (device FP64) or NULL */
+} bcm_adjoint_out;
+
+/* Fill opts with the defaults listed in bcm_solver_opts. */
+void bcm_default_opts(bcm_solver_opts* opts);
+
+/* Validate and copy a mesh description (host only, no GPU call).  Errors:
+ * BCM_ERR_INVALID_ARG (NULL pointers, bad n), BCM_ERR_INVALID_MESH (the offending cube and
+ * face are named in bcm_last_error).  Destroy with bcm_mesh_destroy. */
+int bcm_mesh_create(const bcm_mesh_desc* desc, bcm_mesh** out);
+void bcm_mesh_destroy(bcm_mesh* mesh);
+
+/* Plan the solver for a mesh and options (host only, no GPU call) and report the device
+ * workspace it needs in *workspace_bytes.  The plan keeps a reference to the mesh, which
+ * must outlive it. */
+int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan** out,
+                    size_t* workspace_bytes);
+void bcm_plan_destroy(bcm_plan* plan);
+
+/* Bind a caller-owned device buffer (>= workspace_bytes, 256-byte aligned) to the plan and
+ * upload the mesh metadata into it on `stream`.  BCM_ERR_WORKSPACE if too small. */
+int bcm_plan_bind(bcm_plan* plan, void* d_workspace, size_t bytes, void* stream);
+
+/* One projection step (Sec. 3, forcing -> Poisson -> correction).  The Poisson solve runs to
+ * opts.tol; BCM_NOT_CONVERGED if the limits are hit first (outputs valid), BCM_ERR_NONFINITE
+ * if a residual norm is not finite.  report may be NULL. */
+int bcm_project(bcm_plan* plan, const bcm_project_in* in, bcm_project_out* out,
+                bcm_report* report, void* stream);
+
+/* The projection step with a given pressure (no solve): forcing and correction only.  Used
+ * to recompute the velocities of a step from a checkpointed pressure. */
+int bcm_project_recompute(bcm_plan* plan, const bcm_project_in* in, const double* d_p,
+                          bcm_project_out* out, void* stream);
+
+/* Adjoint (reverse-mode derivative) of bcm_project: the transposed correction, the
+ * transposed Poisson solve (A^T = V A V^{-1}, V = cell volumes), and the transposed face
+ * interpolation, divergence and forcing.  Solver options as for the forward call. */
+int bcm_project_adjoint(bcm_plan* plan, const bcm_adjoint_in* in, bcm_adjoint_out* out,
+                        bcm_report* report, void* stream);
+
+/* Solve the pressure Poisson equation A p = b (Sec. 3) for a device FP64 right-hand side;
+ * d_p holds the initial guess on entry if use_guess != 0 (else zero) and the solution on
+ * exit. */
+int bcm_poisson_solve(bcm_plan* plan, const double* d_b, double* d_p, int use_guess,
+                      bcm_report* report, void* stream);
+
+/* Apply the 7-point operator of the Poisson equation, in FP64: d_Ap = A d_p. */
+int bcm_apply_laplacian(bcm_plan* plan, const double* d_p, double* d_Ap, void* stream);
+
+/* Kernel timing: when enabled, every launch of the named kernel class is bracketed by HIP
+ * events on the launch stream; bcm_timing_read returns the number of timed launches and
+ * their summed duration (milliseconds), synchronising the events.  Classes are listed by
+ * bcm_timing_name(i) for i = 0.. until it returns NULL. */
+int bcm_timing_enable(bcm_plan* plan, const char* kernel_class);
+int bcm_timing_read(bcm_plan* plan, int64_t* launches, double* total_ms);
+const char* bcm_timing_name(int i);
+
+/* Bytes and cell counts the plan's mesh implies (for throughput reporting). */
+int64_t bcm_mesh_cells(const bcm_mesh* mesh);
+
+const char* bcm_status_string(int status);
+const char* bcm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCM_H */

@@ -1,0 +1,214 @@
+// Kernel argument blocks and host launchers of the building-cube library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bcm_internal.hpp"
+
+namespace bcm {
+
+// Device-resident scalars of one Krylov solve (written by k_finalize, read by the kernels).
+struct Scalars {
+  double rr, rr0, bb, zr, zq, pq, alpha, beta, gU, spare[7];
+};
+
+struct Geom {  // what every cube-tiled kernel needs
+  const CubeMeta* meta;
+  const int32_t* launch;
+  int n_cubes;
+  double hscale;  // cell width at this level = meta.h * hscale
+};
+
+template <typename T>
+struct SmoothArgs {
+  Geom g;
+  T* x;                 // iterate (in/out)
+  const T* b;           // right-hand side
+  const T* xf_in;       // faces of x before the launch (unused when zero_init)
+  T* xf_out;            // faces of x after the launch
+  const T* xc;          // coarse correction to add first (level NL/2) or nullptr
+  const T* xcf;         // its faces
+  int sweeps, black_first, zero_init;
+  const T* r_dot;       // fused <x, r_dot>_V and <x, q_dot>_V (level 0 of a Krylov step)
+  const T* q_dot;
+  double* part_zr;
+  double* part_zq;
+};
+
+template <typename T>
+struct RestrictArgs {
+  Geom g;
+  const T* x;
+  const T* xf;
+  const T* b;
+  T* bc;                // restricted residual, level NL/2
+};
+
+template <typename T>
+struct ApplyArgs {      // p = z + beta p (p = z on the first step); q = A p; <p, q>_V
+  Geom g;
+  const T* z;
+  const T* zf;
+  T* p;
+  const T* pf_in;
+  T* pf_out;
+  T* q;
+  const Scalars* sc;
+  int first;
+  double* part;
+};
+
+template <typename T>
+struct UpdateArgs {     // x += alpha p; r -= alpha q; <r, r>_V
+  const CubeMeta* meta;
+  int n_cubes, n3;
+  T* x;
+  const T* p;
+  T* r;
+  const T* q;
+  const Scalars* sc;
+  double* part;
+};
+
+template <typename TO>
+struct Resid64Args {    // r = b - A p in FP64 (or r = A p when b is nullptr); norms
+  Geom g;
+  const double* p;      // nullptr = zero
+  const double* pf;
+  const double* b;
+  TO* r;
+  double* part_rr;
+  double* part_bb;
+  double rscale;        // r is stored multiplied by rscale
+};
+
+template <typename T>
+struct IrArgs {         // p += dscale * d (when d != nullptr); export faces of p
+  Geom g;
+  double* p;
+  const T* d;
+  double* pf_out;
+  double dscale;
+};
+
+template <typename T, typename TO>
+struct ExportArgs {
+  Geom g;
+  const T* x;
+  TO* xf;
+  int comp_faces;       // 1: x is a 3-component field set, face f takes component f >> 1
+  const T* x3[3];
+};
+
+struct FinalizeArgs {
+  const double* p0;
+  const double* p1;
+  int n;
+  Scalars* sc;
+  int op;
+  int first;
+};
+enum { OP_BB = 0, OP_RR0 = 1, OP_ZRZQ = 2, OP_PQ = 3, OP_RR = 4, OP_GU = 5 };
+
+template <typename T>
+struct CoarseArgs {
+  const CubeMeta* meta;
+  int n_cubes;
+  double hscale;
+  const T* b;
+  T* x;
+  T* xf;
+  double* w;            // 4 * n_cubes doubles
+  int iters;
+};
+
+template <typename TF>
+struct ForceArgs {      // u* = (1 - alpha) u~ + alpha u_s; export face-normal components
+  Geom g;
+  const TF* u[3];
+  const TF* alpha;
+  const TF* us[3];
+  double usc[3];
+  TF* ustar[3];
+  TF* uf;
+};
+
+template <typename TF>
+struct DivArgs {        // b = (rho/dt) div(U*)
+  Geom g;
+  const TF* ustar[3];
+  const TF* uf;
+  double U_in, inv_c;
+  double* b;
+  double* part_bb;
+};
+
+template <typename TF>
+struct CorrectArgs {    // u_new = u* - c G_c p; optional face velocities U* - c G p
+  Geom g;
+  const double* p;
+  const double* pf;
+  const TF* ustar[3];
+  const TF* uf;
+  double U_in, c;
+  TF* unew[3];
+  TF* face_u[3];
+};
+
+template <typename TF>
+struct AdjGpArgs {      // out = ((c/h) sum_s sigma_s term_s(v) + g_p) / vol
+  Geom g;
+  const TF* v[3];
+  const TF* vf;
+  const double* gp_in;
+  double c;
+  double* out;
+};
+
+template <typename TF>
+struct AdjRhsArgs {     // g_u* = g_u_new + (1/c) W^T D^T lambda; forcing transpose; g_U_in
+  Geom g;
+  const double* lam;
+  const double* lamf;
+  const TF* gun[3];
+  const TF* u[3];
+  const TF* alpha;
+  const TF* us[3];
+  double usc[3];
+  double inv_c;
+  TF* gu[3];
+  TF* galpha;
+  double* part_gU;
+};
+
+struct ScaleArgs {      // y = x * (vol ^ power) per cube (power = +1 or -1)
+  const CubeMeta* meta;
+  int n_cubes, n3;
+  const double* x;
+  double* y;
+  int power;
+};
+
+// Launchers (return hipError_t of the launch).
+template <typename T> hipError_t launch_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_apply(int NL, const ApplyArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_update(const UpdateArgs<T>& a, hipStream_t s);
+template <typename TO> hipError_t launch_resid64(int NL, const Resid64Args<TO>& a, hipStream_t s);
+template <typename T> hipError_t launch_ir(int NL, const IrArgs<T>& a, hipStream_t s);
+template <typename T, typename TO> hipError_t launch_export(int NL, const ExportArgs<T, TO>& a, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+template <typename T> hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s);
+template <typename TF> hipError_t launch_force(int NL, const ForceArgs<TF>& a, hipStream_t s);
+template <typename TF> hipError_t launch_div(int NL, const DivArgs<TF>& a, hipStream_t s);
+template <typename TF> hipError_t launch_correct(int NL, const CorrectArgs<TF>& a, hipStream_t s);
+template <typename TF> hipError_t launch_adj_gp(int NL, const AdjGpArgs<TF>& a, hipStream_t s);
+template <typename TF> hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a, hipStream_t s);
+hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
+
+inline int cubes_per_wg(int NL) {
+  const int n3 = NL * NL * NL;
+  return n3 >= 256 ? 1 : 256 / n3;
+}
+
+}  // namespace bcm

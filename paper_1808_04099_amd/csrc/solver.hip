@@ -1,0 +1,725 @@
+// Host orchestration of the projection path: workspace plan, multigrid V-cycle coarsened
+// inside each cube with a conjugate-gradient solve on the one-cell-per-cube level (Sec. 3,
+// Sec. 7), flexible CG wrapper, FP64 iterative refinement of FP32 inner solves, projection
+// step (Sec. 3) and its adjoint, exposed through the C ABI of bcm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bcm_internal.hpp"
+#include "kernels.hpp"
+
+namespace bcm {
+
+namespace {
+
+__global__ void k_fill(double* p, size_t n, double v) {
+  for (size_t e = blockIdx.x * size_t(blockDim.x) + threadIdx.x; e < n; e += size_t(gridDim.x) * blockDim.x)
+    p[e] = v;
+}
+__global__ void k_fillf(float* p, size_t n, float v) {
+  for (size_t e = blockIdx.x * size_t(blockDim.x) + threadIdx.x; e < n; e += size_t(gridDim.x) * blockDim.x)
+    p[e] = v;
+}
+
+template <typename T>
+hipError_t fill(T* p, size_t n, hipStream_t s) {
+  const int blocks = int(std::min<size_t>((n + 255) / 256, 65536));
+  if (n == 0) return hipSuccess;
+  if constexpr (sizeof(T) == 8)
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, reinterpret_cast<double*>(p), n, 0.0);
+  else
+    hipLaunchKernelGGL(k_fillf, dim3(blocks), dim3(256), 0, s, reinterpret_cast<float*>(p), n, 0.0f);
+  return hipGetLastError();
+}
+
+const char* const kTimerNames[] = {"smooth16", "smooth8", "smooth4", "smooth2", "restrict16",
+                                   "restrict8", "restrict4", "restrict2", "apply16", "apply8",
+                                   "apply4", "apply2", "update", "resid64", "ir", "coarse",
+                                   "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
+                                   "export", nullptr};
+
+int level_index(int NL) { return NL == 16 ? 0 : NL == 8 ? 1 : NL == 4 ? 2 : 3; }
+
+struct Status {
+  int code = BCM_OK;
+  std::string msg;
+};
+
+}  // namespace
+
+struct Timer {
+  int cls = -1;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+};
+
+}  // namespace bcm
+
+using namespace bcm;
+
+struct bcm_plan {
+  const HostMesh* M = nullptr;
+  bcm_solver_opts o{};
+  int n = 0, nlev = 0, nc = 0;
+  size_t cells = 0;
+  bool inner32 = false, fields32 = false;
+  size_t ws_bytes = 0;
+  char* ws = nullptr;
+  // workspace offsets
+  size_t o_meta = 0, o_launch = 0, o_part[3] = {0, 0, 0}, o_sc = 0, o_cw = 0;
+  size_t o_ustar[3] = {0, 0, 0}, o_uf = 0, o_b64 = 0, o_pf = 0, o_lam = 0;
+  size_t o_r = 0, o_z = 0, o_p = 0, o_q = 0, o_d = 0;
+  size_t o_zf[2] = {0, 0}, o_pfk[2] = {0, 0};
+  std::vector<size_t> o_x, o_b, o_xf[2];  // per level (index 0 unused for x/b: level 0 = z/r)
+  int pf_cur = 0;                         // ping-pong index of the Krylov search-direction faces
+  Timer timer;
+  template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t take(size_t& top, size_t bytes) {
+  const size_t off = top;
+  top += (bytes + kAlign - 1) / kAlign * kAlign;
+  return off;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return BCM_ERR_HIP;
+}
+
+#define HIPCHK(expr, what)                           \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+// Timed launch: when timing is enabled for `cls`, bracket the launch with events.
+template <class F>
+hipError_t timed(bcm_plan* P, int cls, hipStream_t s, F&& launch) {
+  Timer& t = P->timer;
+  const bool on = t.cls == cls;
+  if (on) {
+    if (t.used + 2 > t.ev.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        t.ev.push_back(e);
+      }
+    }
+    hipError_t err = hipEventRecord(t.ev[t.used], s);
+    if (err != hipSuccess) return err;
+  }
+  hipError_t err = launch();
+  if (on) {
+    if (err == hipSuccess) err = hipEventRecord(t.ev[t.used + 1], s);
+    t.used += 2;
+  }
+  return err;
+}
+
+int cls_of(const char* base, int NL) {
+  char name[32];
+  std::snprintf(name, sizeof(name), "%s%d", base, NL);
+  for (int i = 0; kTimerNames[i]; ++i)
+    if (!std::strcmp(kTimerNames[i], name) || !std::strcmp(kTimerNames[i], base)) return i;
+  return -1;
+}
+
+Geom geom(const bcm_plan* P, int NL) {
+  return Geom{P->at<const CubeMeta>(P->o_meta), P->at<const int32_t>(P->o_launch), P->nc,
+              double(P->n) / double(NL)};
+}
+
+int read_scalars(bcm_plan* P, Scalars* host, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(host, P->at<Scalars>(P->o_sc), sizeof(Scalars), hipMemcpyDeviceToHost, s),
+         "scalar readback");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  return BCM_OK;
+}
+
+int finalize(bcm_plan* P, int op, int which0, int which1, int nparts, int first, hipStream_t s) {
+  FinalizeArgs a{P->at<double>(P->o_part[which0]), which1 >= 0 ? P->at<double>(P->o_part[which1]) : nullptr,
+                 nparts, P->at<Scalars>(P->o_sc), op, first};
+  HIPCHK(timed(P, cls_of("finalize", 0), s, [&] { return launch_finalize(a, s); }), "k_finalize");
+  return BCM_OK;
+}
+
+int n_wg(int NL, int nc) {
+  const int c = cubes_per_wg(NL);
+  return (nc + c - 1) / c;
+}
+
+// Export the faces of an FP64 field (k_ir without an update).
+int export64(bcm_plan* P, double* x, double* xf, hipStream_t s) {
+  IrArgs<float> a{geom(P, P->n), x, nullptr, xf, 0.0};
+  HIPCHK(timed(P, cls_of("export", 0), s, [&] { return launch_ir<float>(P->n, a, s); }), "export faces");
+  return BCM_OK;
+}
+
+// One V-cycle on (b_0 = r, x_0 = z): per-cube levels NL = n, n/2, ..., 2 smoothed with
+// red-black Gauss-Seidel, then CG on the one-cell-per-cube level.  At level 0 the final
+// smoothing also accumulates <z, r> and (if q_dot) <z, q>.
+template <typename T>
+int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
+  const int L = P->nlev;
+  auto X = [&](int l) { return l == 0 ? P->at<T>(P->o_z) : P->at<T>(P->o_x[l]); };
+  auto B = [&](int l) { return l == 0 ? P->at<T>(P->o_r) : P->at<T>(P->o_b[l]); };
+  auto F = [&](int ab, int l) { return l == 0 ? P->at<T>(P->o_zf[ab]) : P->at<T>(P->o_xf[ab][l]); };
+  const bcm_solver_opts& o = P->o;
+  for (int l = 0; l < L - 1; ++l) {
+    const int NL = P->n >> l;
+    SmoothArgs<T> sa{};
+    sa.g = geom(P, NL);
+    sa.x = X(l);
+    sa.b = B(l);
+    sa.xf_out = F(0, l);
+    sa.sweeps = o.pre_sweeps;
+    sa.black_first = 0;
+    sa.zero_init = 1;
+    HIPCHK(timed(P, cls_of("smooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "k_smooth (pre)");
+    RestrictArgs<T> ra{geom(P, NL), X(l), F(0, l), B(l), B(l + 1)};
+    HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launch_restrict<T>(NL, ra, s); }), "k_restrict");
+  }
+  CoarseArgs<T> ca{P->at<const CubeMeta>(P->o_meta), P->nc, double(P->n), B(L - 1), X(L - 1),
+                   F(1, L - 1), P->at<double>(P->o_cw), o.coarse_iters};
+  HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse<T>(ca, s); }), "k_coarse");
+  for (int l = L - 2; l >= 0; --l) {
+    const int NL = P->n >> l;
+    SmoothArgs<T> sa{};
+    sa.g = geom(P, NL);
+    sa.x = X(l);
+    sa.b = B(l);
+    sa.xf_in = F(0, l);
+    sa.xf_out = F(1, l);
+    sa.xc = X(l + 1);
+    sa.xcf = F(1, l + 1);
+    sa.sweeps = o.post_sweeps;
+    sa.black_first = 1;
+    sa.zero_init = 0;
+    if (l == 0) {
+      sa.r_dot = B(0);
+      sa.q_dot = q_dot;
+      sa.part_zr = P->at<double>(P->o_part[0]);
+      sa.part_zq = q_dot ? P->at<double>(P->o_part[1]) : nullptr;
+    }
+    HIPCHK(timed(P, cls_of("smooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "k_smooth (post)");
+  }
+  return BCM_OK;
+}
+
+struct SolveLog {
+  bcm_report* rep;
+  int iters = 0;
+  void push(double v) {
+    if (rep && rep->history && rep->history_len < rep->history_cap) rep->history[rep->history_len++] = v;
+  }
+};
+
+// Flexible CG (or plain V-cycle iteration) on A x = r0 with r (= P->o_r) holding the initial
+// residual and x the accumulator.  Stops when the V-weighted <r, r> <= thr (recurrence).
+// hist_scale converts sqrt(<r,r>) to the reported relative residual.
+template <typename T>
+int krylov(bcm_plan* P, T* x, double thr, int max_iter, double hist_scale, SolveLog& log,
+           Scalars* hs, hipStream_t s) {
+  const int NL = P->n;
+  const int nparts = n_wg(NL, P->nc);
+  T* r = P->at<T>(P->o_r);
+  T* z = P->at<T>(P->o_z);
+  T* p = P->at<T>(P->o_p);
+  T* q = P->at<T>(P->o_q);
+  const bool fcg = P->o.krylov != 0;
+  for (int it = 0; it < max_iter; ++it) {
+    int st = vcycle<T>(P, (fcg && it > 0) ? q : nullptr, s);
+    if (st) return st;
+    if ((st = finalize(P, OP_ZRZQ, 0, (fcg && it > 0) ? 1 : -1, nparts, !fcg || it == 0, s))) return st;
+    ApplyArgs<T> aa{geom(P, NL), z, P->at<T>(P->o_zf[1]), p, P->at<T>(P->o_pfk[P->pf_cur]),
+                    P->at<T>(P->o_pfk[P->pf_cur ^ 1]), q, P->at<const Scalars>(P->o_sc),
+                    (!fcg || it == 0) ? 1 : 0, P->at<double>(P->o_part[2])};
+    HIPCHK(timed(P, cls_of("apply", NL), s, [&] { return launch_apply<T>(NL, aa, s); }), "k_apply");
+    P->pf_cur ^= 1;
+    if ((st = finalize(P, OP_PQ, 2, -1, nparts, 0, s))) return st;
+    if (!fcg) {  // stationary iteration: x += z, r -= A z  (alpha = 1)
+      if ((st = finalize(P, OP_PQ, 0, -1, nparts, 0, s))) return st;  // alpha = zr / zr
+    }
+    UpdateArgs<T> ua{P->at<const CubeMeta>(P->o_meta), P->nc, NL * NL * NL, x, p, r, q,
+                     P->at<const Scalars>(P->o_sc), P->at<double>(P->o_part[0])};
+    HIPCHK(timed(P, cls_of("update", 0), s, [&] { return launch_update<T>(ua, s); }), "k_update");
+    if ((st = finalize(P, OP_RR, 0, -1, P->nc, 0, s))) return st;
+    if ((st = read_scalars(P, hs, s))) return st;
+    log.iters++;
+    if (!std::isfinite(hs->rr)) {
+      set_error("non-finite residual in the Krylov iteration");
+      return BCM_ERR_NONFINITE;
+    }
+    log.push(std::sqrt(std::max(hs->rr, 0.0)) * hist_scale);
+    if (hs->rr <= thr) break;
+  }
+  return BCM_OK;
+}
+
+// True FP64 residual of p (faces exported first): <r,r>_V (and <b,b>_V) into the scalars.
+template <typename TO>
+int residual64(bcm_plan* P, const double* p, const double* b, TO* r, double rscale, hipStream_t s) {
+  const int NL = P->n;
+  if (p) {
+    int st = export64(P, const_cast<double*>(p), P->at<double>(P->o_pf), s);
+    if (st) return st;
+  }
+  Resid64Args<TO> ra{geom(P, NL), p, P->at<const double>(P->o_pf), b, r,
+                     P->at<double>(P->o_part[0]), P->at<double>(P->o_part[1]), rscale};
+  HIPCHK(timed(P, cls_of("resid64", 0), s, [&] { return launch_resid64<TO>(NL, ra, s); }), "k_resid64");
+  return finalize(P, OP_BB, 0, 1, n_wg(NL, P->nc), 0, s);
+}
+
+// Solve A p = b to opts.tol (relative, V-weighted, FP64).  p holds the guess if use_guess.
+int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report* rep, hipStream_t s) {
+  const bcm_solver_opts& o = P->o;
+  SolveLog log{rep};
+  if (rep) rep->history_len = 0;
+  Scalars hs{};
+  int st = BCM_OK;
+  int outer = 0;
+  if (!use_guess) HIPCHK(fill<double>(p, P->cells, s), "zero fill");
+  double bb = 0.0, rr = 0.0;
+  const double tol2 = o.tol * o.tol;
+  bool converged = false;
+  if (!P->inner32) {
+    // FP64: flexible CG directly on p, restarted from the true residual if the recurrence
+    // residual and the true one disagree at the end.
+    for (outer = 0; outer < std::max(1, o.max_outer); ++outer) {
+      if ((st = residual64<double>(P, p, b, P->at<double>(P->o_r), 1.0, s))) return st;
+      if ((st = read_scalars(P, &hs, s))) return st;
+      bb = hs.bb;
+      rr = hs.rr;
+      if (!std::isfinite(rr) || !std::isfinite(bb)) {
+        set_error("non-finite right-hand side or residual");
+        return BCM_ERR_NONFINITE;
+      }
+      if (bb == 0.0) {
+        HIPCHK(fill<double>(p, P->cells, s), "zero fill");
+        rr = 0.0;
+        converged = true;
+        break;
+      }
+      log.push(std::sqrt(rr / bb));
+      if (rr <= tol2 * bb) {
+        converged = true;
+        break;
+      }
+      if (log.iters >= o.max_iter) break;
+      if ((st = krylov<double>(P, p, tol2 * bb * 0.25, o.max_iter - log.iters, 1.0 / std::sqrt(bb),
+                               log, &hs, s)))
+        return st;
+    }
+  } else {
+    // Mixed: FP64 residual and update, FP32 inner flexible CG.  The residual handed to the
+    // inner solve is scaled to unit RMS (by the predicted norm) so FP32 range never matters.
+    const double vol = double(P->cells);
+    double rscale = 1.0;
+    for (outer = 0; outer < o.max_outer; ++outer) {
+      float* r32 = P->at<float>(P->o_r);
+      if ((st = residual64<float>(P, (use_guess || outer) ? p : nullptr, b, r32, rscale, s))) return st;
+      if ((st = read_scalars(P, &hs, s))) return st;
+      if (outer == 0) bb = hs.bb;
+      rr = hs.rr;
+      if (!std::isfinite(rr) || !std::isfinite(bb)) {
+        set_error("non-finite right-hand side or residual");
+        return BCM_ERR_NONFINITE;
+      }
+      if (bb == 0.0) {
+        rr = 0.0;
+        converged = true;
+        break;
+      }
+      log.push(std::sqrt(rr / bb));
+      if (rr <= tol2 * bb) {
+        converged = true;
+        break;
+      }
+      if (outer == 0 && !(rscale > 0 && std::fabs(std::log10(rr / vol)) < 20)) {
+        // first pass unscaled and far from unit size: redo the conversion with the true norm
+        rscale = 1.0 / std::sqrt(rr / vol);
+        if ((st = residual64<float>(P, use_guess ? p : nullptr, b, r32, rscale, s))) return st;
+      }
+      float* d = P->at<float>(P->o_d);
+      HIPCHK(fill<float>(d, P->cells, s), "zero fill");
+      const double thr = o.inner_tol * o.inner_tol * rr * rscale * rscale;
+      if ((st = krylov<float>(P, d, thr, o.max_iter, 1.0 / (rscale * std::sqrt(bb)), log, &hs, s)))
+        return st;
+      IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale};
+      HIPCHK(timed(P, cls_of("ir", 0), s, [&] { return launch_ir<float>(P->n, ia, s); }), "k_ir");
+      const double rr_est = hs.rr / (rscale * rscale);
+      if (rr_est > 0 && std::isfinite(rr_est)) rscale = 1.0 / std::sqrt(rr_est / vol);
+    }
+  }
+  if (rep) {
+    rep->n_outer = outer + (converged ? 0 : 0);
+    rep->n_inner = log.iters;
+    rep->final_rel_res = bb > 0 ? std::sqrt(std::max(rr, 0.0) / bb) : 0.0;
+    rep->status = converged ? BCM_OK : BCM_NOT_CONVERGED;
+  }
+  // leave the faces of p exported for the correction kernels
+  if ((st = export64(P, p, P->at<double>(P->o_pf), s))) return st;
+  return converged ? BCM_OK : BCM_NOT_CONVERGED;
+}
+
+// Forcing -> right-hand side -> Poisson -> correction (or, with p_given, forcing and
+// correction only).
+template <typename TF>
+int project_impl(bcm_plan* P, const bcm_project_in* in, bcm_project_out* out, bcm_report* rep,
+                 hipStream_t s, const double* p_given) {
+  const int NL = P->n;
+  const double c = in->dt / in->rho;
+  ForceArgs<TF> fa{};
+  fa.g = geom(P, NL);
+  fa.alpha = static_cast<const TF*>(in->alpha);
+  for (int d = 0; d < 3; ++d) {
+    fa.u[d] = static_cast<const TF*>(in->u[d]);
+    fa.us[d] = static_cast<const TF*>(in->us[d]);
+    fa.usc[d] = in->us_const[d];
+    fa.ustar[d] = P->at<TF>(P->o_ustar[d]);
+  }
+  fa.uf = P->at<TF>(P->o_uf);
+  HIPCHK(timed(P, cls_of("force", 0), s, [&] { return launch_force<TF>(NL, fa, s); }), "k_force");
+  double* p = out->p;
+  int st = BCM_OK;
+  if (!p_given) {
+    DivArgs<TF> da{geom(P, NL), {fa.ustar[0], fa.ustar[1], fa.ustar[2]}, fa.uf, in->U_in, 1.0 / c,
+                   P->at<double>(P->o_b64), nullptr};
+    HIPCHK(timed(P, cls_of("div", 0), s, [&] { return launch_div<TF>(NL, da, s); }), "k_div");
+    bool guess = false;
+    if (in->p0) {
+      if (in->p0 != p)
+        HIPCHK(hipMemcpyAsync(p, in->p0, P->cells * sizeof(double), hipMemcpyDeviceToDevice, s), "copy p0");
+      guess = true;
+    }
+    st = poisson(P, P->at<const double>(P->o_b64), p, guess, rep, s);
+    if (st < 0) return st;
+  } else {
+    p = const_cast<double*>(p_given);
+    int e = export64(P, p, P->at<double>(P->o_pf), s);
+    if (e) return e;
+  }
+  CorrectArgs<TF> ca{};
+  ca.g = geom(P, NL);
+  ca.p = p;
+  ca.pf = P->at<const double>(P->o_pf);
+  for (int d = 0; d < 3; ++d) {
+    ca.ustar[d] = fa.ustar[d];
+    ca.unew[d] = static_cast<TF*>(out->u_new[d]);
+    ca.face_u[d] = static_cast<TF*>(out->face_u[d]);
+  }
+  ca.uf = fa.uf;
+  ca.U_in = in->U_in;
+  ca.c = c;
+  HIPCHK(timed(P, cls_of("correct", 0), s, [&] { return launch_correct<TF>(NL, ca, s); }), "k_correct");
+  return st;
+}
+
+// Adjoint of project_impl: g_p = -c G^T G_c^T g_u (+ g_p); lam = V A^{-1} (g_p / V);
+// g_u* = g_u + (1/c) W^T D^T lam; g_u~ = (1 - alpha) g_u*; g_alpha; g_U_in.
+template <typename TF>
+int adjoint_impl(bcm_plan* P, const bcm_adjoint_in* in, bcm_adjoint_out* out, bcm_report* rep,
+                 hipStream_t s) {
+  const int NL = P->n;
+  const double c = in->dt / in->rho;
+  TF* vf = P->at<TF>(P->o_uf);
+  ExportArgs<TF, TF> ea{};
+  ea.g = geom(P, NL);
+  ea.xf = vf;
+  ea.comp_faces = 1;
+  for (int d = 0; d < 3; ++d) ea.x3[d] = static_cast<const TF*>(in->g_u_new[d]);
+  HIPCHK(timed(P, cls_of("export", 0), s, [&] { return launch_export<TF, TF>(NL, ea, s); }), "export g_u faces");
+  AdjGpArgs<TF> ga{};
+  ga.g = geom(P, NL);
+  for (int d = 0; d < 3; ++d) ga.v[d] = ea.x3[d];
+  ga.vf = vf;
+  ga.gp_in = in->g_p;
+  ga.c = c;
+  ga.out = P->at<double>(P->o_b64);
+  HIPCHK(timed(P, cls_of("adj_gp", 0), s, [&] { return launch_adj_gp<TF>(NL, ga, s); }), "k_adj_gp");
+  double* lam = P->at<double>(P->o_lam);
+  int st = poisson(P, P->at<const double>(P->o_b64), lam, false, rep, s);
+  if (st < 0) return st;
+  if (P->M->multilevel) {
+    ScaleArgs sa{P->at<const CubeMeta>(P->o_meta), P->nc, NL * NL * NL, lam, lam, +1};
+    HIPCHK(launch_scale(sa, s), "k_scale");
+  }
+  int e = export64(P, lam, P->at<double>(P->o_pf), s);
+  if (e) return e;
+  AdjRhsArgs<TF> ra{};
+  ra.g = geom(P, NL);
+  ra.lam = lam;
+  ra.lamf = P->at<const double>(P->o_pf);
+  ra.alpha = static_cast<const TF*>(in->alpha);
+  for (int d = 0; d < 3; ++d) {
+    ra.gun[d] = ea.x3[d];
+    ra.u[d] = static_cast<const TF*>(in->u[d]);
+    ra.us[d] = static_cast<const TF*>(in->us[d]);
+    ra.usc[d] = in->us_const[d];
+    ra.gu[d] = static_cast<TF*>(out->g_u[d]);
+  }
+  ra.galpha = static_cast<TF*>(out->g_alpha);
+  ra.inv_c = 1.0 / c;
+  ra.part_gU = P->at<double>(P->o_part[0]);
+  HIPCHK(timed(P, cls_of("adj_rhs", 0), s, [&] { return launch_adj_rhs<TF>(NL, ra, s); }), "k_adj_rhs");
+  if ((e = finalize(P, OP_GU, 0, -1, n_wg(NL, P->nc), 0, s))) return e;
+  Scalars hs{};
+  if ((e = read_scalars(P, &hs, s))) return e;
+  out->g_U_in = hs.gU;
+  if (out->lambda)
+    HIPCHK(hipMemcpyAsync(out->lambda, lam, P->cells * sizeof(double), hipMemcpyDeviceToDevice, s), "copy lambda");
+  return st;
+}
+
+int check_bound(const bcm_plan* P) {
+  if (!P) {
+    set_error("NULL plan");
+    return BCM_ERR_INVALID_ARG;
+  }
+  if (!P->ws) {
+    set_error("no workspace bound to the plan (bcm_plan_bind)");
+    return BCM_ERR_WORKSPACE;
+  }
+  return BCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bcm_default_opts(bcm_solver_opts* o) {
+  if (!o) return;
+  o->precision = BCM_FP64;
+  o->tol = 1e-10;
+  o->max_iter = 50;
+  o->max_outer = 10;
+  o->inner_tol = 1e-5;
+  o->pre_sweeps = 2;
+  o->post_sweeps = 2;
+  o->coarse_iters = 10;
+  o->krylov = 1;
+}
+
+int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan** out,
+                    size_t* workspace_bytes) {
+  if (!mesh || !out) {
+    set_error("bcm_plan_create: NULL argument");
+    return BCM_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  bcm_solver_opts o;
+  if (opts)
+    o = *opts;
+  else
+    bcm_default_opts(&o);
+  if (o.precision < BCM_FP64 || o.precision > BCM_MIXED_F32FIELDS || !(o.tol > 0.0) || o.max_iter < 1 ||
+      o.max_outer < 1 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.pre_sweeps < 0 ||
+      o.post_sweeps < 0 || o.coarse_iters < 0 || o.pre_sweeps > 16 || o.post_sweeps > 16) {
+    set_error("bcm_plan_create: invalid solver options");
+    return BCM_ERR_INVALID_ARG;
+  }
+  auto* P = new (std::nothrow) bcm_plan;
+  if (!P) {
+    set_error("bcm_plan_create: out of host memory");
+    return BCM_ERR_INVALID_ARG;
+  }
+  const HostMesh& M = mesh->m;
+  P->M = &M;
+  P->o = o;
+  P->n = M.n;
+  P->nc = M.n_cubes;
+  P->nlev = 1;
+  while ((M.n >> (P->nlev - 1)) > 1) P->nlev++;
+  P->cells = size_t(M.n_cubes) * M.n * M.n * M.n;
+  P->inner32 = o.precision != BCM_FP64;
+  P->fields32 = o.precision == BCM_MIXED_F32FIELDS;
+  const size_t Ti = P->inner32 ? 4 : 8, Tf = P->fields32 ? 4 : 8;
+  const size_t nc = size_t(M.n_cubes), n2 = size_t(M.n) * M.n, cells = P->cells;
+  size_t top = 0;
+  P->o_meta = take(top, nc * sizeof(CubeMeta));
+  P->o_launch = take(top, nc * sizeof(int32_t));
+  for (int i = 0; i < 3; ++i) P->o_part[i] = take(top, nc * sizeof(double));
+  P->o_sc = take(top, sizeof(Scalars));
+  P->o_cw = take(top, 4 * nc * sizeof(double));
+  for (int d = 0; d < 3; ++d) P->o_ustar[d] = take(top, cells * Tf);
+  P->o_uf = take(top, 6 * n2 * nc * Tf);
+  P->o_b64 = take(top, cells * 8);
+  P->o_pf = take(top, 6 * n2 * nc * 8);
+  P->o_lam = take(top, cells * 8);
+  P->o_r = take(top, cells * Ti);
+  P->o_z = take(top, cells * Ti);
+  P->o_p = take(top, cells * Ti);
+  P->o_q = take(top, cells * Ti);
+  P->o_d = P->inner32 ? take(top, cells * 4) : 0;
+  for (int i = 0; i < 2; ++i) {
+    P->o_zf[i] = take(top, 6 * n2 * nc * Ti);
+    P->o_pfk[i] = take(top, 6 * n2 * nc * Ti);
+  }
+  P->o_x.assign(P->nlev, 0);
+  P->o_b.assign(P->nlev, 0);
+  P->o_xf[0].assign(P->nlev, 0);
+  P->o_xf[1].assign(P->nlev, 0);
+  for (int l = 1; l < P->nlev; ++l) {
+    const size_t NL = size_t(M.n >> l);
+    P->o_x[l] = take(top, nc * NL * NL * NL * Ti);
+    P->o_b[l] = take(top, nc * NL * NL * NL * Ti);
+    P->o_xf[0][l] = take(top, 6 * NL * NL * nc * Ti);
+    P->o_xf[1][l] = take(top, 6 * NL * NL * nc * Ti);
+  }
+  P->ws_bytes = top;
+  if (workspace_bytes) *workspace_bytes = top;
+  *out = P;
+  return BCM_OK;
+}
+
+void bcm_plan_destroy(bcm_plan* P) {
+  if (!P) return;
+  for (hipEvent_t e : P->timer.ev) (void)hipEventDestroy(e);
+  delete P;
+}
+
+int bcm_plan_bind(bcm_plan* P, void* d_ws, size_t bytes, void* stream) {
+  if (!P || !d_ws) {
+    set_error("bcm_plan_bind: NULL argument");
+    return BCM_ERR_INVALID_ARG;
+  }
+  if (bytes < P->ws_bytes || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) {
+    set_error("bcm_plan_bind: workspace smaller than bcm_plan_create reported, or not 256-byte aligned");
+    return BCM_ERR_WORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  P->ws = static_cast<char*>(d_ws);
+  const HostMesh& M = *P->M;
+  HIPCHK(hipMemcpyAsync(P->ws + P->o_meta, M.meta.data(), M.meta.size() * sizeof(CubeMeta),
+                        hipMemcpyHostToDevice, s), "upload cube metadata");
+  HIPCHK(hipMemcpyAsync(P->ws + P->o_launch, M.launch.data(), M.launch.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice, s), "upload launch order");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  return BCM_OK;
+}
+
+int bcm_project(bcm_plan* P, const bcm_project_in* in, bcm_project_out* out, bcm_report* rep,
+                void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!in || !out || !out->p || !in->u[0] || !in->u[1] || !in->u[2] || !(in->dt > 0) || !(in->rho > 0)) {
+    set_error("bcm_project: NULL field or non-positive dt / rho");
+    return BCM_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = P->fields32 ? project_impl<float>(P, in, out, rep, s, nullptr)
+                   : project_impl<double>(P, in, out, rep, s, nullptr);
+  if (rep) rep->status = st;
+  return st;
+}
+
+int bcm_project_recompute(bcm_plan* P, const bcm_project_in* in, const double* d_p,
+                          bcm_project_out* out, void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!in || !out || !d_p || !in->u[0] || !in->u[1] || !in->u[2] || !(in->dt > 0) || !(in->rho > 0)) {
+    set_error("bcm_project_recompute: NULL field or non-positive dt / rho");
+    return BCM_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return P->fields32 ? project_impl<float>(P, in, out, nullptr, s, d_p)
+                     : project_impl<double>(P, in, out, nullptr, s, d_p);
+}
+
+int bcm_project_adjoint(bcm_plan* P, const bcm_adjoint_in* in, bcm_adjoint_out* out,
+                        bcm_report* rep, void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!in || !out || !in->u[0] || !in->u[1] || !in->u[2] || !in->g_u_new[0] || !in->g_u_new[1] ||
+      !in->g_u_new[2] || !out->g_u[0] || !out->g_u[1] || !out->g_u[2] || !(in->dt > 0) ||
+      !(in->rho > 0) || (in->alpha && !out->g_alpha)) {
+    set_error("bcm_project_adjoint: NULL field or non-positive dt / rho");
+    return BCM_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = P->fields32 ? adjoint_impl<float>(P, in, out, rep, s) : adjoint_impl<double>(P, in, out, rep, s);
+  if (rep) rep->status = st;
+  return st;
+}
+
+int bcm_poisson_solve(bcm_plan* P, const double* d_b, double* d_p, int use_guess, bcm_report* rep,
+                      void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!d_b || !d_p) {
+    set_error("bcm_poisson_solve: NULL field");
+    return BCM_ERR_INVALID_ARG;
+  }
+  st = poisson(P, d_b, d_p, use_guess != 0, rep, static_cast<hipStream_t>(stream));
+  if (rep) rep->status = st;
+  return st;
+}
+
+int bcm_apply_laplacian(bcm_plan* P, const double* d_p, double* d_Ap, void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!d_p || !d_Ap) {
+    set_error("bcm_apply_laplacian: NULL field");
+    return BCM_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = export64(P, const_cast<double*>(d_p), P->at<double>(P->o_pf), s))) return st;
+  Resid64Args<double> ra{geom(P, P->n), d_p, P->at<const double>(P->o_pf), nullptr, d_Ap, nullptr, nullptr, 1.0};
+  HIPCHK(timed(P, cls_of("resid64", 0), s, [&] { return launch_resid64<double>(P->n, ra, s); }), "k_resid64 (apply)");
+  return BCM_OK;
+}
+
+int bcm_timing_enable(bcm_plan* P, const char* name) {
+  if (!P) {
+    set_error("bcm_timing_enable: NULL plan");
+    return BCM_ERR_INVALID_ARG;
+  }
+  P->timer.used = 0;
+  P->timer.cls = -1;
+  if (!name || !*name) return BCM_OK;
+  for (int i = 0; kTimerNames[i]; ++i)
+    if (!std::strcmp(kTimerNames[i], name)) {
+      P->timer.cls = i;
+      return BCM_OK;
+    }
+  set_error(std::string("bcm_timing_enable: unknown kernel class ") + name);
+  return BCM_ERR_INVALID_ARG;
+}
+
+int bcm_timing_read(bcm_plan* P, int64_t* launches, double* total_ms) {
+  if (!P || !launches || !total_ms) {
+    set_error("bcm_timing_read: NULL argument");
+    return BCM_ERR_INVALID_ARG;
+  }
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < P->timer.used; i += 2) {
+    HIPCHK(hipEventSynchronize(P->timer.ev[i + 1]), "event synchronize");
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, P->timer.ev[i], P->timer.ev[i + 1]), "event elapsed time");
+    tot += ms;
+  }
+  *launches = int64_t(P->timer.used / 2);
+  *total_ms = tot;
+  return BCM_OK;
+}
+
+const char* bcm_timing_name(int i) {
+  if (i < 0) return nullptr;
+  for (int k = 0; kTimerNames[k]; ++k)
+    if (k == i) return kTimerNames[k];
+  return nullptr;
+}
+
+}  // extern "C"

@@ -1,0 +1,287 @@
+// LDS tile machinery shared by the stencil kernels (device code).
+//
+// A workgroup owns CPB cubes of NL^3 cells at one multigrid level.  Each cube is staged in
+// LDS as an (NL+2)^3 tile: the cube's cells plus a one-cell halo on its six faces (no edges
+// or corners: the 7-point stencil never reads them).  Halo values come from the face
+// buffers of the neighbouring cubes: every field with a halo carries a buffer
+// faces[cube][face][t2][t1] of the cube's own boundary layer (t1, t2 = tangential cell
+// indices, first tangential axis fastest), written by the kernel that produced the field.
+// The halo fill reads those contiguous 1-D slabs instead of strided columns of the
+// neighbour's cube, and applies the face relation:
+//   same level    -> the neighbour's boundary cell;
+//   coarser (2:1) -> the coarse cell covering this fine cell's face quadrant;
+//   finer (2:1)   -> the mean of the 2x2 fine cells covering this cell's face;
+//   domain boundary -> nothing (the boundary enters through the per-side own coefficient).
+// The raw neighbour value is scaled per relation by the rule of the operator being applied
+// (RuleP, RuleU, RuleV, RuleL below) so that, after staging, every side of every cell reads
+//   neighbour term = int_scale * tile[neighbour]   and   own term = own(side) * x_cell
+// with own(side) = int_own inside the cube and the rule's table value on cube faces.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bcm_internal.hpp"
+
+namespace bcm {
+
+constexpr int WG = 256;
+
+template <int NL>
+struct Lv {
+  static constexpr int N = NL, N2 = NL * NL, N3 = NL * NL * NL;
+  static constexpr int T = NL + 2, T2 = T * T, TILE = T * T * T;
+  static constexpr int CPB = (N3 >= WG) ? 1 : WG / N3;  // cubes per workgroup
+  static constexpr int FACE = 6 * N2;                   // face-buffer values per cube
+};
+
+template <int NL>
+__device__ __forceinline__ int ti(int i, int j, int k) {
+  constexpr int T = NL + 2;
+  return ((k + 1) * T + (j + 1)) * T + (i + 1);
+}
+
+// Cell of face f (0..5 = -x,+x,-y,+y,-z,+z) at tangential position (t1, t2).
+template <int NL>
+__device__ __forceinline__ void face_cell(int f, int t1, int t2, int& i, int& j, int& k) {
+  const int lay = (f & 1) ? NL - 1 : 0;
+  const int d = f >> 1;
+  i = d == 0 ? lay : t1;
+  j = d == 1 ? lay : (d == 0 ? t1 : t2);
+  k = d == 2 ? lay : t2;
+}
+
+template <int NL>
+__device__ __forceinline__ int halo_idx(int f, int t1, int t2) {
+  const int lay = (f & 1) ? NL : -1;
+  const int d = f >> 1;
+  if (d == 0) return ti<NL>(lay, t1, t2);
+  if (d == 1) return ti<NL>(t1, lay, t2);
+  return ti<NL>(t1, t2, lay);
+}
+
+// Raw neighbour value across face f of a cube at tangential cell (t1, t2).
+// get(cube, face_of_that_cube, t1, t2) reads one value of that cube's face slab.
+template <int NL, typename T, class Get>
+__device__ __forceinline__ T nb_raw(const CubeMeta& m, int f, int t1, int t2, Get get) {
+  const int of = f ^ 1;
+  const int kd = m.kind[f];
+  if (kd == FK_SAME) return get(m.nbr[f][0], of, t1, t2);
+  if (kd == FK_COARSER) {
+    const int q = m.quad[f];
+    return get(m.nbr[f][0], of, (q & 1) * (NL / 2) + (t1 >> 1), (q >> 1) * (NL / 2) + (t2 >> 1));
+  }
+  if (kd == FK_FINER) {
+    T s = T(0);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int F1 = 2 * t1 + a, F2 = 2 * t2 + b;
+        s += get(m.nbr[f][(F1 / NL) + 2 * (F2 / NL)], of, F1 % NL, F2 % NL);
+      }
+    return s * T(0.25);
+  }
+  return T(0);
+}
+
+// ---- operator rules (indexed by FaceKind: SAME, COARSER, FINER, OUTFLOW, INFLOW, SLIP) ----
+// RuleP: 7-point Laplacian / face gradient of the pressure.  Side term = nb - own * x, so
+//   (A x)_i = sum_sides (nb - own x_i) / h^2,  outward face derivative = (nb - own x_i) / h.
+//   2:1 ghosts: fine side (2/3)(P - x) (centre distance 3h/2), coarse side (4/3)(mean - x).
+// RuleU: face-normal velocity U = nb + own * u (linear interpolation to the face; inflow
+//   faces carry the prescribed U_in, slip faces zero, open faces the boundary-cell value).
+// RuleV: transpose of (cell gradient o face gradient): term = own * v + nb.
+// RuleL: transpose of (face interpolation o divergence): term = own * lambda - nb.
+enum Rule { RULE_P = 0, RULE_U = 1, RULE_V = 2, RULE_L = 3 };
+
+template <int R>
+struct RuleTab;
+template <>
+struct RuleTab<RULE_P> {
+  static constexpr double int_scale = 1.0, int_own = 1.0;
+  __device__ static double nbeff(int k) { return k == FK_SAME ? 1.0 : k == FK_COARSER ? 2.0 / 3.0 : k == FK_FINER ? 4.0 / 3.0 : 0.0; }
+  __device__ static double own(int k) {
+    return k == FK_SAME ? 1.0 : k == FK_COARSER ? 2.0 / 3.0 : k == FK_FINER ? 4.0 / 3.0 : k == FK_OUTFLOW ? 2.0 : 0.0;
+  }
+};
+template <>
+struct RuleTab<RULE_U> {
+  static constexpr double int_scale = 0.5, int_own = 0.5;
+  // halo stores neighbour contribution / int_scale
+  __device__ static double nbeff(int k) { return k == FK_SAME ? 1.0 : k == FK_COARSER ? 2.0 / 3.0 : k == FK_FINER ? 4.0 / 3.0 : 0.0; }
+  __device__ static double own(int k) {
+    return k == FK_SAME ? 0.5 : k == FK_COARSER ? 2.0 / 3.0 : k == FK_FINER ? 1.0 / 3.0 : k == FK_OUTFLOW ? 1.0 : 0.0;
+  }
+};
+template <>
+struct RuleTab<RULE_V> {
+  static constexpr double int_scale = 0.5, int_own = 0.5;
+  __device__ static double nbeff(int k) { return k == FK_SAME ? 1.0 : k == FK_COARSER ? 1.0 / 6.0 : k == FK_FINER ? 16.0 / 3.0 : 0.0; }
+  __device__ static double own(int k) {
+    return k == FK_SAME ? 0.5 : k == FK_COARSER ? 1.0 / 3.0 : k == FK_FINER ? 2.0 / 3.0 : k == FK_OUTFLOW ? 1.0 : 0.0;
+  }
+};
+template <>
+struct RuleTab<RULE_L> {
+  static constexpr double int_scale = 0.5, int_own = 0.5;
+  __device__ static double nbeff(int k) { return k == FK_SAME ? 1.0 : k == FK_COARSER ? 1.0 / 6.0 : k == FK_FINER ? 16.0 / 3.0 : 0.0; }
+  __device__ static double own(int k) {
+    return k == FK_SAME ? 0.5 : k == FK_COARSER ? 2.0 / 3.0 : k == FK_FINER ? 1.0 / 3.0 : k == FK_OUTFLOW ? 1.0 : 0.0;
+  }
+};
+
+// Stage the metadata of the workgroup's cubes in LDS.
+template <int NL>
+__device__ __forceinline__ void load_meta(CubeMeta* sm, int* cube, const CubeMeta* meta,
+                                          const int32_t* launch, int n_cubes) {
+  constexpr int CPB = Lv<NL>::CPB;
+  const int base = blockIdx.x * CPB;
+  for (int e = threadIdx.x; e < CPB * 32; e += blockDim.x) {
+    const int s = e >> 5, w = e & 31;
+    const int g = base + s;
+    const int c = g < n_cubes ? launch[g] : -1;
+    if (w == 0) cube[s] = c;
+    reinterpret_cast<int32_t*>(&sm[s])[w] = c >= 0 ? reinterpret_cast<const int32_t*>(&meta[c])[w] : 0;
+  }
+  __syncthreads();
+}
+
+// Decompose a workgroup-local cell index into (slot, i, j, k).
+template <int NL>
+__device__ __forceinline__ void cell_of(int e, int& s, int& i, int& j, int& k) {
+  constexpr int N3 = Lv<NL>::N3;
+  s = e / N3;
+  const int c = e - s * N3;
+  i = c % NL;
+  j = (c / NL) % NL;
+  k = c / (NL * NL);
+}
+
+// Own coefficient of the side (face f) of cell (i,j,k) under rule R.
+template <int NL, int R>
+__device__ __forceinline__ double side_own(const CubeMeta& m, int f, int i, int j, int k) {
+  const int d = f >> 1;
+  const int c = d == 0 ? i : d == 1 ? j : k;
+  const bool on = (f & 1) ? (c == NL - 1) : (c == 0);
+  return on ? RuleTab<R>::own(m.kind[f]) : RuleTab<R>::int_own;
+}
+
+// Fill the six halo slabs of every cube of the workgroup under rule R.
+// get(cube, face, t1, t2) returns a raw face value of a neighbour (see nb_raw);
+// bcval(m, f) returns the value stored for a domain-boundary face (already / int_scale).
+template <int NL, int R, typename T, class Get, class BcVal>
+__device__ __forceinline__ void fill_halo(T* tile, const CubeMeta* sm, const int* cube, Get get,
+                                          BcVal bcval, int fmask = 0x3F) {
+  constexpr int CPB = Lv<NL>::CPB, N2 = Lv<NL>::N2, TILE = Lv<NL>::TILE;
+  for (int e = threadIdx.x; e < CPB * 6 * N2; e += blockDim.x) {
+    const int s = e / (6 * N2);
+    const int r = e - s * 6 * N2;
+    const int f = r / N2;
+    const int t = r - f * N2;
+    const int t1 = t % NL, t2 = t / NL;
+    if (cube[s] < 0 || !((fmask >> f) & 1)) continue;
+    const CubeMeta& m = sm[s];
+    const int kd = m.kind[f];
+    T v;
+    if (kd <= FK_FINER)
+      v = T(RuleTab<R>::nbeff(kd)) * nb_raw<NL, T>(m, f, t1, t2, get);
+    else
+      v = bcval(m, f);
+    tile[s * TILE + halo_idx<NL>(f, t1, t2)] = v;
+  }
+}
+
+// Write the boundary layer of each staged cube into its face buffer.
+template <int NL, typename T, typename TO>
+__device__ __forceinline__ void export_faces(TO* faces, const T* tile, const int* cube) {
+  constexpr int CPB = Lv<NL>::CPB, N2 = Lv<NL>::N2, TILE = Lv<NL>::TILE;
+  for (int e = threadIdx.x; e < CPB * 6 * N2; e += blockDim.x) {
+    const int s = e / (6 * N2);
+    const int r = e - s * 6 * N2;
+    const int f = r / N2;
+    const int t = r - f * N2;
+    if (cube[s] < 0) continue;
+    int i, j, k;
+    face_cell<NL>(f, t % NL, t / NL, i, j, k);
+    faces[(size_t)cube[s] * 6 * N2 + r] = TO(tile[s * TILE + ti<NL>(i, j, k)]);
+  }
+}
+
+// Deterministic workgroup sum (fixed shuffle tree, then waves in order); valid on thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) t += sh[w];
+  return t;
+}
+
+// ---- face getters and stencil helpers ----
+template <int NL, typename T>
+struct FaceGet {
+  const T* f;
+  __device__ T operator()(int c, int of, int t1, int t2) const {
+    return f[(size_t)c * 6 * NL * NL + of * NL * NL + t2 * NL + t1];
+  }
+};
+
+template <int NL, typename T>
+struct FaceGetAxpy {  // a + beta * b
+  const T* a;
+  const T* b;
+  T beta;
+  __device__ T operator()(int c, int of, int t1, int t2) const {
+    const size_t o = (size_t)c * 6 * NL * NL + of * NL * NL + t2 * NL + t1;
+    return a[o] + beta * b[o];
+  }
+};
+
+template <int NL, typename T>
+struct FaceGetProlong {  // fine face value (or 0) + coarse face value of the covering coarse cell
+  const T* f;
+  const T* fc;
+  __device__ T operator()(int c, int of, int t1, int t2) const {
+    constexpr int NC = NL / 2;
+    T v = f ? f[(size_t)c * 6 * NL * NL + of * NL * NL + t2 * NL + t1] : T(0);
+    return v + fc[(size_t)c * 6 * NC * NC + of * NC * NC + (t2 >> 1) * NC + (t1 >> 1)];
+  }
+};
+
+template <typename T>
+struct BcZero {
+  __device__ T operator()(const CubeMeta&, int) const { return T(0); }
+};
+
+// (sum of the six neighbour terms, sum of the six own coefficients) of cell (i,j,k) under RULE_P.
+template <int NL, typename T>
+__device__ __forceinline__ void stencil_p(const T* t, const CubeMeta& m, int i, int j, int k,
+                                          T& nb, T& dg) {
+  const int c = ti<NL>(i, j, k);
+  constexpr int T1 = NL + 2, T2 = (NL + 2) * (NL + 2);
+  nb = t[c - 1] + t[c + 1] + t[c - T1] + t[c + T1] + t[c - T2] + t[c + T2];
+  T d = T(6);
+  if (i == 0) d += T(RuleTab<RULE_P>::own(m.kind[0])) - T(1);
+  if (i == NL - 1) d += T(RuleTab<RULE_P>::own(m.kind[1])) - T(1);
+  if (j == 0) d += T(RuleTab<RULE_P>::own(m.kind[2])) - T(1);
+  if (j == NL - 1) d += T(RuleTab<RULE_P>::own(m.kind[3])) - T(1);
+  if (k == 0) d += T(RuleTab<RULE_P>::own(m.kind[4])) - T(1);
+  if (k == NL - 1) d += T(RuleTab<RULE_P>::own(m.kind[5])) - T(1);
+  dg = d;
+}
+
+template <int NL, typename T>
+__device__ __forceinline__ void zero_halo(T* tile, const int* cube) {
+  constexpr int CPB = Lv<NL>::CPB, N2 = Lv<NL>::N2, TILE = Lv<NL>::TILE;
+  for (int e = threadIdx.x; e < CPB * 6 * N2; e += blockDim.x) {
+    const int s = e / (6 * N2);
+    const int r = e - s * 6 * N2;
+    const int f = r / N2, t = r - f * N2;
+    tile[s * TILE + halo_idx<NL>(f, t % NL, t / NL)] = T(0);
+  }
+}
+
+}  // namespace bcm

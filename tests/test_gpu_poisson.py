@@ -1,0 +1,87 @@
+"""GPU parity of the Poisson operator and solve (FP64 and mixed) against the FP64 oracle.
+
+Tolerances: the FP64 operator apply is one stencil evaluation, compared to 1e-12 of the
+largest value.  Solves run to a V-weighted relative residual of 1e-10 (the workload target);
+the oracle re-evaluates the residual of the returned pressure in FP64 (<= 1.2e-10, the slack
+covering the different summation order), and the error against the exact discrete solution
+is bounded by ||e|| <= ||r|| / lambda_min(-A) with lambda_min in closed form on one level.
+"""
+import numpy as np
+import pytest
+
+from bcm_inputs import CHANNEL_BC, OPEN_BC, configs, uniform_mesh
+from oracle import FVMesh, UniformGrid
+
+from gpu_util import dev, host, log, plan_for, rel_err, requires_gpu
+from test_oracle_operators import _tiny_multilevel
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def _meshes():
+    return {
+        "channel_n4": uniform_mesh((3, 2, 2), 0.25, 4, CHANNEL_BC),
+        "open_n8": uniform_mesh((2, 2, 2), 0.5, 8, OPEN_BC),
+        "channel_n16": uniform_mesh((4, 2, 2), 0.25, 16, CHANNEL_BC),
+        "tiny_3level_n2": _tiny_multilevel(),
+        "multilevel_small_n4": configs.multilevel_small()["mesh"],
+    }
+
+
+@pytest.mark.parametrize("name", sorted(_meshes()))
+def test_laplacian_apply_matches_oracle(name):
+    m = _meshes()[name]
+    log(f"laplacian {name}: {m.n_cubes} cubes n={m.n}")
+    fv = FVMesh(m)
+    p = np.random.default_rng(5).standard_normal(m.n_cells)
+    plan = plan_for(m)
+    ap = host(plan.apply_laplacian(dev(p)))
+    ref = fv.A @ p
+    assert rel_err(ap, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_manufactured_solution_small_box(precision):
+    """4x4x4 cubes of 16^3, open box: p_h = (-14 pi^2 / lambda_h) sin sin sin exactly."""
+    pr = configs.small_box()
+    m = pr["mesh"]
+    log(f"manufactured {precision}")
+    plan = plan_for(m, precision)
+    p, rep = plan.poisson_solve(dev(pr["b"]))
+    p = host(p)
+    fv = FVMesh(m)
+    rr = fv.residual_norm(p, pr["b"].ravel())
+    log(f"  iters={rep.n_inner} outer={rep.n_outer} reported={rep.final_rel_res:.3e} "
+        f"oracle={rr:.3e}")
+    assert rep.status == 0 and rep.final_rel_res <= 1e-10
+    assert rr <= 1.2e-10
+    h = 1.0 / 64
+    lam_h = sum(2 * np.cos(k * np.pi * h) - 2 for k in (1, 2, 3)) / h ** 2
+    X, Y, Z = m.cell_centres()
+    ph = (-14 * np.pi ** 2 / lam_h) * (np.sin(np.pi * X) * np.sin(2 * np.pi * Y)
+                                        * np.sin(3 * np.pi * Z)).ravel()
+    ug = UniformGrid(m)
+    bound = rr * np.linalg.norm(pr["b"]) / ug.lambda_min_abs()
+    assert np.linalg.norm(p - ph) <= 1.01 * bound
+
+
+@pytest.mark.parametrize("name", ["channel_n4", "open_n8", "tiny_3level_n2",
+                                  "multilevel_small_n4"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_poisson_matches_oracle(name, precision):
+    m = _meshes()[name]
+    log(f"poisson {name} {precision}")
+    fv = FVMesh(m)
+    b = np.random.default_rng(9).standard_normal(m.n_cells)
+    plan = plan_for(m, precision)
+    p, rep = plan.poisson_solve(dev(b))
+    p = host(p)
+    rr = fv.residual_norm(p, b)
+    log(f"  iters={rep.n_inner} outer={rep.n_outer} reported={rep.final_rel_res:.3e} "
+        f"oracle={rr:.3e}")
+    assert rep.status == 0
+    assert rr <= 1.2e-10
+    ref = fv.solve(b)
+    # ||e||_V <= ||r||_V / lambda_min of the V-symmetric operator; checked loosely via the
+    # residual and directly against the exact solve
+    assert rel_err(p, ref) <= 1e-7
