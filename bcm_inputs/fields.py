@@ -169,9 +169,34 @@ def fourier_field(mesh: Mesh, seed: int, n_modes: int = 32, kmax: int = 8, lengt
     k, a, phi = fourier_modes(seed, n_modes, kmax)
     L = np.asarray(length if length is not None else
                    np.subtract(mesh.domain_hi, mesh.domain_lo), dtype=np.float64)
+    if np.all(mesh.level == mesh.level[0]):
+        return _fourier_field_uniform(mesh, k, a, phi, L)
     X, Y, Z = mesh.cell_centres()
     out = np.zeros_like(X)
     for m in range(n_modes):
         out += a[m] * np.cos(2.0 * np.pi * (k[m, 0] * X / L[0] + k[m, 1] * Y / L[1]
                                             + k[m, 2] * Z / L[2]) + phi[m])
+    return out
+
+
+def _fourier_field_uniform(mesh: Mesh, k, a, phi, L):
+    """Same sum on a single-level mesh, evaluated separably on the global grid:
+    sum_m a_m Re(e^{i phi_m} e^{i kx x} e^{i ky y} e^{i kz z}) as one (x,y) x m x z product."""
+    n = mesh.n
+    h = float(mesh.h()[0])
+    lo = np.asarray(mesh.domain_lo, dtype=np.float64)
+    cijk = np.rint((mesh.origin - lo) / (h * n)).astype(np.int64)
+    dims = cijk.max(axis=0) + 1
+    N = dims * n
+    xs = [lo[d] + (np.arange(N[d]) + 0.5) * h for d in range(3)]
+    ex = np.exp(1j * 2.0 * np.pi * np.outer(k[:, 0], xs[0]) / L[0]) * (a * np.exp(1j * phi))[:, None]
+    ey = np.exp(1j * 2.0 * np.pi * np.outer(k[:, 1], xs[1]) / L[1])
+    ez = np.exp(1j * 2.0 * np.pi * np.outer(k[:, 2], xs[2]) / L[2])
+    # M[(y, x), m] = ey[m, y] ex[m, x];  G[z, y, x] = Re(sum_m ez[m, z] M[(y, x), m])
+    M = (ey[:, :, None] * ex[:, None, :]).reshape(ex.shape[0], -1)       # [m, y*x]
+    G = (ez.T @ M).real.reshape(N[2], N[1], N[0])
+    out = np.empty((mesh.n_cubes, n, n, n))
+    for c in range(mesh.n_cubes):
+        x, y, z = cijk[c]
+        out[c] = G[z * n:(z + 1) * n, y * n:(y + 1) * n, x * n:(x + 1) * n]
     return out

@@ -100,11 +100,16 @@ typedef struct {
   double tol;           /* target ||b - A p||_V / ||b||_V, evaluated in FP64       [1e-10] */
   int32_t max_iter;     /* Krylov iterations per solve (FP64 mode) / per inner solve   [50] */
   int32_t max_outer;    /* mixed modes: FP64 refinement steps                          [10] */
-  double inner_tol;     /* mixed modes: relative tolerance of each FP32 inner solve  [1e-5] */
+  double inner_tol;     /* mixed modes: relative tolerance of each FP32 inner solve  [1e-6] */
   int32_t pre_sweeps;   /* red-black Gauss-Seidel sweeps before restriction             [2] */
   int32_t post_sweeps;  /* sweeps after prolongation                                    [2] */
-  int32_t coarse_iters; /* CG iterations on the one-cell-per-cube level                 [10] */
+  int32_t coarse_iters; /* CG iterations on the one-cell-per-cube level (coarse_solver 0),
+                           or on the smallest cube-graph level (coarse_solver 1)       [10] */
   int32_t krylov;       /* 1 = flexible CG preconditioned by one V-cycle, 0 = V-cycles  [1] */
+  int32_t coarse_solver;/* one-cell-per-cube level: 0 = CG only (the paper's scheme),
+                           1 = multigrid on the cube graph (octree, then lattice merging;
+                           box-shaped domains, otherwise 0 is used)                     [1] */
+  int32_t coarse_cycles;/* coarse_solver 1: V-cycles per coarse solve                    [2] */
 } bcm_solver_opts;
 
 /* Per-call solver report (host memory). */
@@ -136,6 +141,8 @@ typedef struct {
   void* face_u[3];       /* optional corrected face-normal velocities, or NULL each:
                             face_u[d] is [cube][k][j][i] with n+1 entries along axis d
                             (x: [n][n][n+1], y: [n][n+1][n], z: [n+1][n][n]) */
+  double* b;             /* optional: the Poisson right-hand side (rho/dt) div U* that was
+                            solved (device, FP64), or NULL */
 } bcm_project_out;
 
 /* Inputs of the adjoint of one projection step (same forward inputs, no pressure needed:

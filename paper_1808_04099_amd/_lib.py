@@ -22,7 +22,8 @@ class MeshDesc(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("tol", c_double), ("max_iter", c_int32),
                 ("max_outer", c_int32), ("inner_tol", c_double), ("pre_sweeps", c_int32),
-                ("post_sweeps", c_int32), ("coarse_iters", c_int32), ("krylov", c_int32)]
+                ("post_sweeps", c_int32), ("coarse_iters", c_int32), ("krylov", c_int32),
+                ("coarse_solver", c_int32), ("coarse_cycles", c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -38,7 +39,8 @@ class ProjectIn(ctypes.Structure):
 
 
 class ProjectOut(ctypes.Structure):
-    _fields_ = [("u_new", c_void_p * 3), ("p", c_void_p), ("face_u", c_void_p * 3)]
+    _fields_ = [("u_new", c_void_p * 3), ("p", c_void_p), ("face_u", c_void_p * 3),
+                ("b", c_void_p)]
 
 
 class AdjointIn(ctypes.Structure):

@@ -153,8 +153,9 @@ class Plan:
 
     # -- entry points --------------------------------------------------------------------------
     def project(self, u, alpha, U_in, dt, rho, us=(0.0, 0.0, 0.0), p0=None, face_u=False,
-                out=None, history=4096):
-        """One projection step; returns dict(u_new=[3], p, report, face_u=[3] or None)."""
+                out=None, history=4096, want_b=False):
+        """One projection step; returns dict(u_new=[3], p, report, face_u=[3] or None,
+        b = the solved Poisson right-hand side or None)."""
         u = [self._field(x, f"u[{d}]") for d, x in enumerate(u)]
         alpha = self._field(alpha, "alpha")
         us_t = [self._field(x, "us") if torch.is_tensor(x) else None for x in us]
@@ -170,10 +171,11 @@ class Plan:
                                                   for t in us_t]),
                           (ctypes.c_double * 3)(*usc), float(U_in), float(dt), float(rho),
                           _ptr(p0).value)
+        b = self.empty(torch.float64) if want_b else None
         pout = L.ProjectOut((ctypes.c_void_p * 3)(*[x.data_ptr() for x in out["u_new"]]),
                             out["p"].data_ptr(),
                             (ctypes.c_void_p * 3)(*[t.data_ptr() if t is not None else None
-                                                    for t in fu]))
+                                                    for t in fu]), _ptr(b).value)
         rep, hist = _report(history)
         st = self._lib.bcm_project(self.handle, ctypes.byref(pin), ctypes.byref(pout),
                                    ctypes.byref(rep), _stream())
@@ -181,6 +183,7 @@ class Plan:
         out = dict(out)
         out["report"] = _unpack(rep, hist)
         out["face_u"] = fu if face_u else None
+        out["b"] = b
         return out
 
     def project_recompute(self, u, alpha, p, U_in, dt, rho, us=(0.0, 0.0, 0.0), out=None):

@@ -3,7 +3,8 @@
 Projection           one step (u~, alpha, U_in) -> (u^{n+1}, p); backward calls the hand-written
                      adjoint kernels (transposed correction, transposed Poisson solve, transposed
                      face interpolation / divergence / forcing) through bcm_project_adjoint.
-MultiStepProjection  K steps u^{k+1} = P(F(u^k)) with per-step pressure checkpoints: forward keeps
+MultiStepProjection  K steps u^{k+1} = P(F(u^k)) with per-step pressure checkpoints (each solve warm-started from the previous
+                     step's pressure): forward keeps
                      u^0 and p^0..p^{K-1} only; backward recomputes each u^k from u^0 with
                      bcm_project_recompute (forcing + correction, no solve) and runs the adjoint
                      steps in reverse.
@@ -44,12 +45,12 @@ class Projection(torch.autograd.Function):
 
 class MultiStepProjection(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, ux, uy, uz, alpha, U_in, plan, dt, rho, steps, warm_start=True):
+    def forward(ctx, ux, uy, uz, alpha, U_in, plan, dt, rho, steps):
         U = float(U_in)
         u = [ux, uy, uz]
         ps, reports = [], []
         for _ in range(int(steps)):
-            out = plan.project(u, alpha, U, dt, rho, p0=ps[-1] if (warm_start and ps) else None)
+            out = plan.project(u, alpha, U, dt, rho, p0=ps[-1] if ps else None)
             ps.append(out["p"])
             reports.append(out["report"])
             u = out["u_new"]
@@ -75,7 +76,7 @@ class MultiStepProjection(torch.autograd.Function):
                 g_alpha += ga
             gU += gu_in
         return (g[0], g[1], g[2], g_alpha, torch.tensor(gU, dtype=torch.float64),
-                None, None, None, None, None)
+                None, None, None, None)
 
 
 def kinetic_energy(u, cell_volume, rho=1.0):

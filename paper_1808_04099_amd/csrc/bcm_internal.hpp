@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "bcm.h"
+#include "coarse.hpp"
 
 namespace bcm {
 
@@ -44,6 +45,7 @@ struct HostMesh {
   int max_level = 0;
   bool multilevel = false;
   bool has_inflow = false;
+  CoarseHierarchy coarse;         // multigrid levels of the one-cell-per-cube graph
 };
 
 void set_error(const std::string& msg);

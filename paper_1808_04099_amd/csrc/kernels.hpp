@@ -205,6 +205,7 @@ template <typename TF> hipError_t launch_correct(int NL, const CorrectArgs<TF>& 
 template <typename TF> hipError_t launch_adj_gp(int NL, const AdjGpArgs<TF>& a, hipStream_t s);
 template <typename TF> hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a, hipStream_t s);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
+template <typename T> hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s);
 
 inline int cubes_per_wg(int NL) {
   const int n3 = NL * NL * NL;

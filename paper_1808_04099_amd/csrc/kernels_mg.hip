@@ -439,6 +439,123 @@ __global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Multigrid on the cube graph (one unknown per cube), one workgroup: multicolour
+// Gauss-Seidel on every graph level, volume-weighted restriction, piecewise-constant
+// prolongation, CG on the last (smallest) level.  Runs `cycles` V-cycles from x = 0.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__device__ void g_smooth(const GLevel<T>& L, int sweeps, bool forward) {
+  for (int s = 0; s < sweeps; ++s)
+    for (int cc = 0; cc < L.ncol; ++cc) {
+      const int c = forward ? cc : L.ncol - 1 - cc;
+      const int o1 = L.color_off[c + 1];
+      for (int k = L.color_off[c] + threadIdx.x; k < o1; k += blockDim.x) {
+        const int i = L.order[k];
+        T acc = L.b[i];
+        for (int e = L.row[i]; e < L.row[i + 1]; ++e) acc -= L.val[e] * L.x[L.col[e]];
+        L.x[i] = acc / L.diag[i];
+      }
+      __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ void g_residual(const GLevel<T>& L) {
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+    T acc = L.b[i] - L.diag[i] * L.x[i];
+    for (int e = L.row[i]; e < L.row[i + 1]; ++e) acc -= L.val[e] * L.x[L.col[e]];
+    L.r[i] = acc;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void g_bottom(const GLevel<T>& L, int iters, double* w, double* red) {
+  // CG on the symmetric positive definite (-V A) x = -V b (V = relative node volume).
+  double* xv = w;
+  double* rv = w + L.n;
+  double* pv = w + 2 * L.n;
+  double* qv = w + 3 * L.n;
+  double rr = 0.0;
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+    const double r = -double(L.vol[i]) * double(L.b[i]);
+    xv[i] = 0.0;
+    rv[i] = r;
+    pv[i] = r;
+    rr += r * r;
+  }
+  rr = block_sum_all(rr, red);
+  const double stop = 1e-20 * rr;
+  for (int it = 0; it < iters && rr > stop; ++it) {
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+      double acc = double(L.diag[i]) * pv[i];
+      for (int e = L.row[i]; e < L.row[i + 1]; ++e) acc += double(L.val[e]) * pv[L.col[e]];
+      acc *= -double(L.vol[i]);
+      qv[i] = acc;
+      pq += pv[i] * acc;
+    }
+    pq = block_sum_all(pq, red);
+    if (!(pq > 0.0)) break;
+    const double al = rr / pq;
+    double rn = 0.0;
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+      xv[i] += al * pv[i];
+      rv[i] -= al * qv[i];
+      rn += rv[i] * rv[i];
+    }
+    rn = block_sum_all(rn, red);
+    const double be = rn / rr;
+    rr = rn;
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) pv[i] = rv[i] + be * pv[i];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.x[i] = T(xv[i]);
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
+  __shared__ double red[16];
+  __shared__ GLevel<T> lv[kMaxGraphLevels];
+  if (threadIdx.x < a.nlev) lv[threadIdx.x] = a.lev[threadIdx.x];
+  __syncthreads();
+  const int G = a.nlev;
+  for (int i = threadIdx.x; i < lv[0].n; i += blockDim.x) {
+    lv[0].b[i] = a.b_in[i];
+    lv[0].x[i] = T(0);
+  }
+  __syncthreads();
+  for (int cy = 0; cy < a.cycles; ++cy) {
+    for (int g = 0; g + 1 < G; ++g) {
+      g_smooth(lv[g], a.pre, true);
+      g_residual(lv[g]);
+      const GLevel<T>& C = lv[g + 1];
+      for (int J = threadIdx.x; J < C.n; J += blockDim.x) {
+        T acc = T(0);
+        for (int e = C.child_row[J]; e < C.child_row[J + 1]; ++e) acc += C.child_w[e] * lv[g].r[C.child[e]];
+        C.b[J] = acc;
+        C.x[J] = T(0);
+      }
+      __syncthreads();
+    }
+    g_bottom(lv[G - 1], a.bottom_iters, a.w, red);
+    for (int g = G - 2; g >= 0; --g) {
+      const GLevel<T>& F = lv[g];
+      for (int i = threadIdx.x; i < F.n; i += blockDim.x) F.x[i] += lv[g + 1].x[F.parent[i]];
+      __syncthreads();
+      g_smooth(F, a.post, false);
+    }
+  }
+  for (int i = threadIdx.x; i < lv[0].n; i += blockDim.x) {
+    const T v = lv[0].x[i];
+    a.x_out[i] = v;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) a.xf_out[(size_t)i * 6 + f] = v;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_scale(ScaleArgs a) {
   const int c = blockIdx.x;
   const double w = a.power > 0 ? a.meta[c].vol : 1.0 / a.meta[c].vol;
@@ -509,6 +626,14 @@ hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s) {
   hipLaunchKernelGGL((k_coarse<T>), dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_coarse_mg<T>), dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_coarse_mg<float>(const CoarseMGArgs<float>&, hipStream_t);
+template hipError_t launch_coarse_mg<double>(const CoarseMGArgs<double>&, hipStream_t);
+
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3(a.n_cubes), dim3(WG), 0, s, a);
   return hipGetLastError();

@@ -194,6 +194,9 @@ void derive(HostMesh& M) {
       const int p = x * chunk + i;
       if (p < nc) M.launch.push_back(order[p]);
     }
+  build_coarse_hierarchy(M, M.coarse, kMaxGraphLevels);
+  for (const CoarseLevel& L : M.coarse.levels)
+    if (int(L.color_off.size()) - 1 > 8) M.coarse.ok = false;  // device keeps 8 colours
 }
 
 }  // namespace

@@ -38,7 +38,8 @@ hipError_t fill(T* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-const char* const kTimerNames[] = {"smooth16", "smooth8", "smooth4", "smooth2", "restrict16",
+const char* const kTimerNames[] = {"presmooth16", "presmooth8", "presmooth4", "presmooth2",
+                                   "postsmooth16", "postsmooth8", "postsmooth4", "postsmooth2", "restrict16",
                                    "restrict8", "restrict4", "restrict2", "apply16", "apply8",
                                    "apply4", "apply2", "update", "resid64", "ir", "coarse",
                                    "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
@@ -78,6 +79,13 @@ struct bcm_plan {
   size_t o_zf[2] = {0, 0}, o_pfk[2] = {0, 0};
   std::vector<size_t> o_x, o_b, o_xf[2];  // per level (index 0 unused for x/b: level 0 = z/r)
   int pf_cur = 0;                         // ping-pong index of the Krylov search-direction faces
+  // cube-graph multigrid (coarse_solver 1)
+  bool graph = false;
+  struct GOff {
+    size_t row, col, val, diag, vol, order, parent, child_row, child, child_w, x, b, r;
+  };
+  std::vector<GOff> g_off;
+  size_t o_glev = 0, o_gw = 0;
   Timer timer;
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
@@ -187,13 +195,21 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
     sa.sweeps = o.pre_sweeps;
     sa.black_first = 0;
     sa.zero_init = 1;
-    HIPCHK(timed(P, cls_of("smooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "k_smooth (pre)");
+    HIPCHK(timed(P, cls_of("presmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "k_smooth (pre)");
     RestrictArgs<T> ra{geom(P, NL), X(l), F(0, l), B(l), B(l + 1)};
     HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launch_restrict<T>(NL, ra, s); }), "k_restrict");
   }
-  CoarseArgs<T> ca{P->at<const CubeMeta>(P->o_meta), P->nc, double(P->n), B(L - 1), X(L - 1),
-                   F(1, L - 1), P->at<double>(P->o_cw), o.coarse_iters};
-  HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse<T>(ca, s); }), "k_coarse");
+  if (P->graph) {
+    CoarseMGArgs<T> ga{B(L - 1), X(L - 1), F(1, L - 1), P->at<const GLevel<T>>(P->o_glev),
+                       int(P->g_off.size()), o.coarse_cycles, 2, 2,
+                       std::max(o.coarse_iters, 64),  // the last graph level has <= 64 nodes
+                       P->at<double>(P->o_gw)};
+    HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse_mg<T>(ga, s); }), "k_coarse_mg");
+  } else {
+    CoarseArgs<T> ca{P->at<const CubeMeta>(P->o_meta), P->nc, double(P->n), B(L - 1), X(L - 1),
+                     F(1, L - 1), P->at<double>(P->o_cw), o.coarse_iters};
+    HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse<T>(ca, s); }), "k_coarse");
+  }
   for (int l = L - 2; l >= 0; --l) {
     const int NL = P->n >> l;
     SmoothArgs<T> sa{};
@@ -213,7 +229,7 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
       sa.part_zr = P->at<double>(P->o_part[0]);
       sa.part_zq = q_dot ? P->at<double>(P->o_part[1]) : nullptr;
     }
-    HIPCHK(timed(P, cls_of("smooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "k_smooth (post)");
+    HIPCHK(timed(P, cls_of("postsmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "k_smooth (post)");
   }
   return BCM_OK;
 }
@@ -354,7 +370,11 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
       }
       float* d = P->at<float>(P->o_d);
       HIPCHK(fill<float>(d, P->cells, s), "zero fill");
-      const double thr = o.inner_tol * o.inner_tol * rr * rscale * rscale;
+      // reduce the residual by inner_tol, or only by what is still missing to reach tol
+      // (with a factor 0.3 of margin), whichever is the weaker requirement
+      const double need = 0.3 * o.tol * std::sqrt(bb / rr);
+      const double red_target = std::max(o.inner_tol, std::min(need, 0.1));
+      const double thr = red_target * red_target * rr * rscale * rscale;
       if ((st = krylov<float>(P, d, thr, o.max_iter, 1.0 / (rscale * std::sqrt(bb)), log, &hs, s)))
         return st;
       IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale};
@@ -406,6 +426,9 @@ int project_impl(bcm_plan* P, const bcm_project_in* in, bcm_project_out* out, bc
     }
     st = poisson(P, P->at<const double>(P->o_b64), p, guess, rep, s);
     if (st < 0) return st;
+    if (out->b)
+      HIPCHK(hipMemcpyAsync(out->b, P->at<const double>(P->o_b64), P->cells * sizeof(double),
+                            hipMemcpyDeviceToDevice, s), "copy b");
   } else {
     p = const_cast<double*>(p_given);
     int e = export64(P, p, P->at<double>(P->o_pf), s);
@@ -483,6 +506,60 @@ int adjoint_impl(bcm_plan* P, const bcm_adjoint_in* in, bcm_adjoint_out* out, bc
   return st;
 }
 
+// Upload the cube-graph hierarchy (converted to the inner precision T) and its level table.
+template <typename T>
+int upload_graph(bcm_plan* P, hipStream_t s) {
+  const auto& Ls = P->M->coarse.levels;
+  std::vector<std::vector<T>> keep;
+  std::vector<GLevel<T>> lev(Ls.size());
+  auto put = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(P->ws + off, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  auto conv = [&](const std::vector<double>& v) -> const std::vector<T>& {
+    keep.emplace_back(v.begin(), v.end());
+    return keep.back();
+  };
+  keep.reserve(4 * Ls.size());
+  for (size_t g = 0; g < Ls.size(); ++g) {
+    const CoarseLevel& L = Ls[g];
+    const bcm_plan::GOff& o = P->g_off[g];
+    HIPCHK(put(o.row, L.row.data(), L.row.size() * 4), "upload graph rows");
+    HIPCHK(put(o.col, L.col.data(), L.col.size() * 4), "upload graph columns");
+    HIPCHK(put(o.val, conv(L.val).data(), L.val.size() * sizeof(T)), "upload graph values");
+    HIPCHK(put(o.diag, conv(L.diag).data(), L.diag.size() * sizeof(T)), "upload graph diagonal");
+    HIPCHK(put(o.vol, conv(L.vol).data(), L.vol.size() * sizeof(T)), "upload graph volumes");
+    HIPCHK(put(o.order, L.order.data(), L.order.size() * 4), "upload graph colouring");
+    HIPCHK(put(o.parent, L.parent.data(), L.parent.size() * 4), "upload graph parents");
+    if (g > 0) {
+      HIPCHK(put(o.child_row, L.child_row.data(), L.child_row.size() * 4), "upload graph children");
+      HIPCHK(put(o.child, L.child.data(), L.child.size() * 4), "upload graph children");
+      HIPCHK(put(o.child_w, conv(L.child_w).data(), L.child_w.size() * sizeof(T)), "upload graph weights");
+    }
+    GLevel<T>& d = lev[g];
+    std::memset(&d, 0, sizeof(d));
+    d.n = L.n;
+    d.ncol = int(L.color_off.size()) - 1;
+    for (int c = 0; c <= d.ncol; ++c) d.color_off[c] = L.color_off[c];
+    d.row = P->at<const int32_t>(o.row);
+    d.col = P->at<const int32_t>(o.col);
+    d.val = P->at<const T>(o.val);
+    d.diag = P->at<const T>(o.diag);
+    d.vol = P->at<const T>(o.vol);
+    d.order = P->at<const int32_t>(o.order);
+    d.parent = L.parent.empty() ? nullptr : P->at<const int32_t>(o.parent);
+    d.child_row = g > 0 ? P->at<const int32_t>(o.child_row) : nullptr;
+    d.child = g > 0 ? P->at<const int32_t>(o.child) : nullptr;
+    d.child_w = g > 0 ? P->at<const T>(o.child_w) : nullptr;
+    d.x = P->at<T>(o.x);
+    d.b = P->at<T>(o.b);
+    d.r = P->at<T>(o.r);
+  }
+  HIPCHK(put(P->o_glev, lev.data(), lev.size() * sizeof(GLevel<T>)), "upload graph levels");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  return BCM_OK;
+}
+
 int check_bound(const bcm_plan* P) {
   if (!P) {
     set_error("NULL plan");
@@ -505,11 +582,13 @@ void bcm_default_opts(bcm_solver_opts* o) {
   o->tol = 1e-10;
   o->max_iter = 50;
   o->max_outer = 10;
-  o->inner_tol = 1e-5;
+  o->inner_tol = 1e-6;
   o->pre_sweeps = 2;
   o->post_sweeps = 2;
   o->coarse_iters = 10;
   o->krylov = 1;
+  o->coarse_solver = 1;
+  o->coarse_cycles = 2;
 }
 
 int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan** out,
@@ -526,7 +605,8 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
     bcm_default_opts(&o);
   if (o.precision < BCM_FP64 || o.precision > BCM_MIXED_F32FIELDS || !(o.tol > 0.0) || o.max_iter < 1 ||
       o.max_outer < 1 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.pre_sweeps < 0 ||
-      o.post_sweeps < 0 || o.coarse_iters < 0 || o.pre_sweeps > 16 || o.post_sweeps > 16) {
+      o.post_sweeps < 0 || o.coarse_iters < 0 || o.pre_sweeps > 16 || o.post_sweeps > 16 ||
+      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1) {
     set_error("bcm_plan_create: invalid solver options");
     return BCM_ERR_INVALID_ARG;
   }
@@ -578,6 +658,33 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
     P->o_xf[0][l] = take(top, 6 * NL * NL * nc * Ti);
     P->o_xf[1][l] = take(top, 6 * NL * NL * nc * Ti);
   }
+  P->graph = o.coarse_solver == 1 && M.coarse.ok && !M.coarse.levels.empty();
+  if (P->graph) {
+    const auto& Ls = M.coarse.levels;
+    for (size_t g = 0; g < Ls.size(); ++g) {
+      const CoarseLevel& L = Ls[g];
+      bcm_plan::GOff go{};
+      const size_t n = size_t(L.n), nnz = std::max<size_t>(L.col.size(), 1);
+      go.row = take(top, (n + 1) * 4);
+      go.col = take(top, nnz * 4);
+      go.val = take(top, nnz * Ti);
+      go.diag = take(top, n * Ti);
+      go.vol = take(top, n * Ti);
+      go.order = take(top, n * 4);
+      go.parent = take(top, std::max<size_t>(L.parent.size(), 1) * 4);
+      if (g > 0) {
+        go.child_row = take(top, (n + 1) * 4);
+        go.child = take(top, L.child.size() * 4);
+        go.child_w = take(top, L.child.size() * Ti);
+      }
+      go.x = take(top, n * Ti);
+      go.b = take(top, n * Ti);
+      go.r = take(top, n * Ti);
+      P->g_off.push_back(go);
+    }
+    P->o_glev = take(top, Ls.size() * sizeof(GLevel<double>));
+    P->o_gw = take(top, 4 * size_t(Ls.back().n) * sizeof(double));
+  }
   P->ws_bytes = top;
   if (workspace_bytes) *workspace_bytes = top;
   *out = P;
@@ -607,6 +714,7 @@ int bcm_plan_bind(bcm_plan* P, void* d_ws, size_t bytes, void* stream) {
   HIPCHK(hipMemcpyAsync(P->ws + P->o_launch, M.launch.data(), M.launch.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice, s), "upload launch order");
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  if (P->graph) return P->inner32 ? upload_graph<float>(P, s) : upload_graph<double>(P, s);
   return BCM_OK;
 }
 

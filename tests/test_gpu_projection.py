@@ -1,0 +1,119 @@
+"""GPU parity of the projection step (forcing -> Poisson -> correction) against the oracle.
+
+Tolerances: the pressure comes from a solve to relative residual tol, so the GPU result
+differs from the oracle's exact solve by at most ||e|| <= ||r|| / lambda_min; the velocity
+error is c G_c e.  Both are checked with a fixed 1e-7 relative bound (FP64 fields) or 1e-5
+(FP32 fields, which round u to 6e-8 relative).  The face velocities are checked against the
+exact discrete identity div_f U^{n+1} = (dt/rho) r of the returned pressure.
+"""
+import numpy as np
+import pytest
+
+from bcm_inputs import CHANNEL_BC, configs, uniform_mesh, uniform_random_velocity
+from oracle import FVMesh, projection as OP
+
+from gpu_util import dev, host, log, plan_for, rel_err, requires_gpu
+from test_oracle_operators import _tiny_multilevel
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def _case(name):
+    if name == "channel_n8":
+        m = uniform_mesh((4, 2, 2), 0.25, 8, CHANNEL_BC)
+    elif name == "tiny_3level_n2":
+        m = _tiny_multilevel()
+    elif name == "multilevel_small_n4":
+        m = configs.multilevel_small()["mesh"]
+    elif name == "box_open_n16":
+        m = configs.small_box()["mesh"]
+    rng = np.random.default_rng(21)
+    u = uniform_random_velocity(m, 22, 0.3, (1.0, 0.0, 0.0))
+    alpha = np.clip(rng.uniform(-0.5, 1.5, m.n_cells), 0.0, 1.0)
+    return m, u, alpha
+
+
+def _face_divergence(m, face_u):
+    """div of the returned per-cube face velocities, per cell (cube-local differences)."""
+    n = m.n
+    h = np.repeat(m.h(), n ** 3).reshape(m.n_cubes, n, n, n)
+    fx = face_u[0].reshape(m.n_cubes, n, n, n + 1)
+    fy = face_u[1].reshape(m.n_cubes, n, n + 1, n)
+    fz = face_u[2].reshape(m.n_cubes, n + 1, n, n)
+    return ((np.diff(fx, axis=3) + np.diff(fy, axis=2) + np.diff(fz, axis=1)) / h).ravel()
+
+
+@pytest.mark.parametrize("name", ["channel_n8", "tiny_3level_n2", "multilevel_small_n4",
+                                  "box_open_n16"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_f32fields"])
+def test_projection_matches_oracle(name, precision):
+    m, u, alpha = _case(name)
+    log(f"projection {name} {precision}: {m.n_cubes} cubes")
+    U_in, dt, rho, us = 1.0, 0.3 * float(m.h().min()), 1.2, (0.05, -0.02, 0.01)
+    f32 = precision == "mixed_f32fields"
+    if f32:   # the oracle sees exactly the fields the GPU sees
+        u = u.astype(np.float32).astype(np.float64)
+        alpha = alpha.astype(np.float32).astype(np.float64)
+    fv = FVMesh(m)
+    ref = OP.project(fv, u, alpha, us, U_in, dt, rho)
+    plan = plan_for(m, precision)
+    ft = plan.field_dtype
+    out = plan.project([dev(u[d], ft) for d in range(3)], dev(alpha, ft), U_in, dt, rho, us=us,
+                       face_u=True, want_b=True)
+    rep = out["report"]
+    p = host(out["p"])
+    b = host(out["b"])
+    unew = np.stack([host(x) for x in out["u_new"]])
+    rr = fv.residual_norm(p, b)
+    log(f"  its={rep.n_inner} outer={rep.n_outer} reported={rep.final_rel_res:.2e} "
+        f"oracle={rr:.2e} |b-b_ref|={rel_err(b, ref['b']):.2e}")
+    # the solve: residual of the returned pressure for the right-hand side it solved
+    assert rep.status == 0 and rr <= 1.2e-10
+    # the right-hand side: FP64 fields agree to rounding; FP32 fields store u* rounded to
+    # 6e-8 relative, which the divergence turns into ~1e-7 of max|b|
+    assert rel_err(b, ref["b"]) <= (2e-6 if f32 else 1e-12)
+    tol = 1e-5 if f32 else 1e-7
+    assert rel_err(unew, ref["u_new"]) <= tol
+    assert rel_err(p, ref["p"]) <= tol
+    # the corrected face velocities are divergence free up to c times the final residual
+    div = _face_divergence(m, [host(x) for x in out["face_u"]])
+    c = dt / rho
+    res = c * (b - fv.A @ p)
+    scale = np.abs(fv.D @ ref["U_star"]).max()
+    assert np.abs(div - res).max() <= (1e-6 if f32 else 1e-10) * scale
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_f32fields"])
+def test_recompute_matches_projection(precision):
+    m, u, alpha = _case("multilevel_small_n4")
+    plan = plan_for(m, precision)
+    ft = plan.field_dtype
+    args = ([dev(u[d], ft) for d in range(3)], dev(alpha, ft), 1.0, 0.01, 1.0)
+    out = plan.project(*args)
+    again = plan.project_recompute(args[0], args[1], out["p"], *args[2:])
+    for d in range(3):
+        assert np.array_equal(host(again[d]), host(out["u_new"][d]))
+
+
+def test_sphere_channel_full_size_fp64():
+    """The 1024-cube (4.2M cells) sphere channel, FP64, against the exact spectral oracle."""
+    from oracle import UniformGrid
+    pr = configs.sphere_channel()
+    m = pr["mesh"]
+    log(f"sphere_channel full: {m.n_cells} cells")
+    plan = plan_for(m, "fp64")
+    out = plan.project([dev(pr["u"][d]) for d in range(3)], dev(pr["alpha"]), pr["U_in"],
+                       pr["dt"], pr["rho"])
+    ug = UniformGrid(m)
+    ref = ug.project(pr["u"], pr["alpha"], (0.0, 0.0, 0.0), pr["U_in"], pr["dt"], pr["rho"])
+    p = host(out["p"])
+    r = ref["b_global"] - ug.laplacian(ug.to_global(p))
+    rr = np.linalg.norm(r) / np.linalg.norm(ref["b_global"])
+    rep = out["report"]
+    log(f"  its={rep.n_inner} reported={rep.final_rel_res:.2e} oracle={rr:.2e}")
+    assert rep.status == 0 and rr <= 1.2e-10
+    # ||p - p*|| <= ||r|| / lambda_min (closed form on one level)
+    err = np.linalg.norm(ug.to_global(p) - ref["p_global"])
+    assert err <= 1.01 * np.linalg.norm(r) / ug.lambda_min_abs()
+    unew = np.stack([host(x) for x in out["u_new"]])
+    assert rel_err(unew, ref["u_new"].reshape(3, -1)) <= 1e-7
