@@ -232,6 +232,59 @@ bool build_coarse_hierarchy(const HostMesh& M, CoarseHierarchy& H, int max_level
     }
     cur.swap(next);
   }
+  // device form: renumber every level so that each colour is a contiguous node range,
+  // then store couplings and child lists as column-major ELL arrays
+  std::vector<std::vector<int32_t>> newid(H.levels.size());
+  for (size_t g = 0; g < H.levels.size(); ++g) {
+    const CoarseLevel& L = H.levels[g];
+    newid[g].assign(L.n, 0);
+    for (int p = 0; p < L.n; ++p) newid[g][L.order[p]] = p;
+  }
+  for (size_t g = 0; g < H.levels.size(); ++g) {
+    CoarseLevel& L = H.levels[g];
+    const std::vector<int32_t>& id = newid[g];
+    const int n = L.n;
+    int W = 1;
+    for (int t = 0; t < n; ++t) W = std::max(W, L.row[t + 1] - L.row[t]);
+    L.W = W;
+    L.e_col.assign(size_t(W) * n, 0);
+    L.e_val.assign(size_t(W) * n, 0.0);
+    L.e_diag.assign(n, 0.0);
+    L.e_vol.assign(n, 0.0);
+    for (int t = 0; t < n; ++t) {
+      const int p = id[t];
+      L.e_diag[p] = L.diag[t];
+      L.e_vol[p] = L.vol[t];
+      int w = 0;
+      for (int e = L.row[t]; e < L.row[t + 1]; ++e, ++w) {
+        L.e_col[size_t(w) * n + p] = id[L.col[e]];
+        L.e_val[size_t(w) * n + p] = L.val[e];
+      }
+      for (; w < W; ++w) L.e_col[size_t(w) * n + p] = p;
+    }
+    if (!L.parent.empty()) {
+      const std::vector<int32_t>& idc = newid[g + 1];
+      L.e_parent.assign(n, 0);
+      for (int t = 0; t < n; ++t) L.e_parent[id[t]] = idc[L.parent[t]];
+    }
+    if (g > 0) {
+      const std::vector<int32_t>& idf = newid[g - 1];
+      int CW = 1;
+      for (int t = 0; t < n; ++t) CW = std::max(CW, L.child_row[t + 1] - L.child_row[t]);
+      L.CW = CW;
+      L.e_child.assign(size_t(CW) * n, -1);
+      L.e_child_w.assign(size_t(CW) * n, 0.0);
+      for (int t = 0; t < n; ++t) {
+        const int p = id[t];
+        int w = 0;
+        for (int e = L.child_row[t]; e < L.child_row[t + 1]; ++e, ++w) {
+          L.e_child[size_t(w) * n + p] = idf[L.child[e]];
+          L.e_child_w[size_t(w) * n + p] = L.child_w[e];
+        }
+      }
+    }
+    if (g == 0) L.perm = id;
+  }
   H.ok = true;
   return true;
 }

@@ -10,6 +10,7 @@ struct HostMesh;
 
 struct CoarseLevel {
   int n = 0;
+  // construction (nodes in key order)
   std::vector<int32_t> row, col;      // off-diagonal couplings (CSR)
   std::vector<double> val, diag;      // A_ij and A_ii of the 7-point composite operator
   std::vector<double> vol;            // relative node volume
@@ -18,6 +19,15 @@ struct CoarseLevel {
   std::vector<int32_t> parent;        // node -> node of the next coarser level
   std::vector<int32_t> child_row, child;  // (this level) node -> children on the finer level
   std::vector<double> child_w;        // restriction weights (volume fractions, sum 1)
+  // device form (nodes renumbered so that every colour is contiguous)
+  int W = 0, CW = 0;                  // ELL widths of the couplings and of the child lists
+  std::vector<int32_t> e_col;         // [W][n], padding: own index with value 0
+  std::vector<double> e_val;          // [W][n]
+  std::vector<double> e_diag, e_vol;  // [n]
+  std::vector<int32_t> e_parent;      // [n] (empty on the last level)
+  std::vector<int32_t> e_child;       // [CW][n] children on the finer level, -1 padding
+  std::vector<double> e_child_w;      // [CW][n]
+  std::vector<int32_t> perm;          // level 0: perm[cube] = device node index
 };
 
 struct CoarseHierarchy {
@@ -27,20 +37,19 @@ struct CoarseHierarchy {
 
 bool build_coarse_hierarchy(const HostMesh& M, CoarseHierarchy& H, int max_levels);
 
-// Device view of one graph level (pointers into the plan workspace).
+// Device view of one graph level (pointers into the plan workspace).  x, b and r live in
+// global memory unless lds_* >= 0, in which case the kernel points them into its LDS.
 template <typename T>
 struct GLevel {
-  int n, ncol;
-  int color_off[9];         // up to 8 colours
-  const int32_t* row;
-  const int32_t* col;
-  const T* val;
+  int n, ncol, W, CW;
+  int color_off[9];         // up to 8 colours, contiguous node ranges
+  int lds_x, lds_b, lds_r;  // byte offsets in the kernel's dynamic LDS, or -1
+  const int32_t* col;       // [W][n]
+  const T* val;             // [W][n]
   const T* diag;
   const T* vol;             // relative node volume (V A is symmetric)
-  const int32_t* order;
   const int32_t* parent;    // to the next coarser level (nullptr on the last)
-  const int32_t* child_row; // from the next finer level (nullptr on level 0)
-  const int32_t* child;
+  const int32_t* child;     // [CW][n] from the next finer level (nullptr on level 0)
   const T* child_w;
   T* x;
   T* b;
@@ -55,9 +64,13 @@ struct CoarseMGArgs {
   T* x_out;                 // solution (cube order)
   T* xf_out;                // its face buffer (6 copies per cube)
   const GLevel<T>* lev;     // device array of levels
+  const int32_t* perm0;     // cube -> level-0 node
   int nlev;
   int cycles, pre, post, bottom_iters;
   double* w;                // CG work space for the bottom level (4 * n_last doubles)
+  int lds_bytes;            // dynamic LDS the launch reserves for the lds_* placements
 };
+
+constexpr int kGraphLdsBudget = 128 * 1024;
 
 }  // namespace bcm

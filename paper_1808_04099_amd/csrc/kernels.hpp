@@ -207,9 +207,26 @@ template <typename TF> hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s);
 
+// Persistent 16^3 kernels (kernels_fine.hip).  Their grid never exceeds fine_grid(n_cubes);
+// they write fine_grid(n_cubes) partial sums (zeros past their own grid).
+__host__ __device__ inline int fine_grid(int n_cubes) { return n_cubes < 4096 ? n_cubes : 4096; }
+template <typename T> hipError_t launch16_smooth(const SmoothArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch16_restrict(const RestrictArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch16_apply(const ApplyArgs<T>& a, hipStream_t s);
+template <typename TO> hipError_t launch16_resid64(const Resid64Args<TO>& a, hipStream_t s);
+
+// Number of partial sums a tiled kernel at level NL writes.
+inline int partials_of(int NL, int n_cubes);
+
 inline int cubes_per_wg(int NL) {
   const int n3 = NL * NL * NL;
   return n3 >= 256 ? 1 : 256 / n3;
+}
+
+inline int partials_of(int NL, int n_cubes) {
+  if (NL == 16) return fine_grid(n_cubes);
+  const int c = cubes_per_wg(NL);
+  return (n_cubes + c - 1) / c;
 }
 
 }  // namespace bcm

@@ -444,29 +444,33 @@ __global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
 // Gauss-Seidel on every graph level, volume-weighted restriction, piecewise-constant
 // prolongation, CG on the last (smallest) level.  Runs `cycles` V-cycles from x = 0.
 // ------------------------------------------------------------------------------------------
+// sum_w val[w][i] * x[col[w][i]] (column-major ELL: the loads of all w are independent)
+template <typename T>
+__device__ __forceinline__ T g_offdiag(const GLevel<T>& L, const T* x, int i) {
+  T acc = T(0);
+  for (int w = 0; w < L.W; ++w) {
+    const size_t o = size_t(w) * L.n + i;
+    acc += L.val[o] * x[L.col[o]];
+  }
+  return acc;
+}
+
 template <typename T>
 __device__ void g_smooth(const GLevel<T>& L, int sweeps, bool forward) {
   for (int s = 0; s < sweeps; ++s)
     for (int cc = 0; cc < L.ncol; ++cc) {
       const int c = forward ? cc : L.ncol - 1 - cc;
       const int o1 = L.color_off[c + 1];
-      for (int k = L.color_off[c] + threadIdx.x; k < o1; k += blockDim.x) {
-        const int i = L.order[k];
-        T acc = L.b[i];
-        for (int e = L.row[i]; e < L.row[i + 1]; ++e) acc -= L.val[e] * L.x[L.col[e]];
-        L.x[i] = acc / L.diag[i];
-      }
+      for (int i = L.color_off[c] + threadIdx.x; i < o1; i += blockDim.x)
+        L.x[i] = (L.b[i] - g_offdiag(L, L.x, i)) / L.diag[i];
       __syncthreads();
     }
 }
 
 template <typename T>
 __device__ void g_residual(const GLevel<T>& L) {
-  for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
-    T acc = L.b[i] - L.diag[i] * L.x[i];
-    for (int e = L.row[i]; e < L.row[i + 1]; ++e) acc -= L.val[e] * L.x[L.col[e]];
-    L.r[i] = acc;
-  }
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x)
+    L.r[i] = L.b[i] - L.diag[i] * L.x[i] - g_offdiag(L, L.x, i);
   __syncthreads();
 }
 
@@ -491,7 +495,10 @@ __device__ void g_bottom(const GLevel<T>& L, int iters, double* w, double* red) 
     double pq = 0.0;
     for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
       double acc = double(L.diag[i]) * pv[i];
-      for (int e = L.row[i]; e < L.row[i + 1]; ++e) acc += double(L.val[e]) * pv[L.col[e]];
+      for (int w = 0; w < L.W; ++w) {
+        const size_t o = size_t(w) * L.n + i;
+        acc += double(L.val[o]) * pv[L.col[o]];
+      }
       acc *= -double(L.vol[i]);
       qv[i] = acc;
       pq += pv[i] * acc;
@@ -517,13 +524,21 @@ __device__ void g_bottom(const GLevel<T>& L, int iters, double* w, double* red) 
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char gsm[];
   __shared__ double red[16];
   __shared__ GLevel<T> lv[kMaxGraphLevels];
-  if (threadIdx.x < a.nlev) lv[threadIdx.x] = a.lev[threadIdx.x];
+  if (threadIdx.x < a.nlev) {
+    GLevel<T> L = a.lev[threadIdx.x];
+    if (L.lds_x >= 0) L.x = reinterpret_cast<T*>(gsm + L.lds_x);
+    if (L.lds_b >= 0) L.b = reinterpret_cast<T*>(gsm + L.lds_b);
+    if (L.lds_r >= 0) L.r = reinterpret_cast<T*>(gsm + L.lds_r);
+    lv[threadIdx.x] = L;
+  }
   __syncthreads();
   const int G = a.nlev;
-  for (int i = threadIdx.x; i < lv[0].n; i += blockDim.x) {
-    lv[0].b[i] = a.b_in[i];
+  for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
+    const int i = a.perm0[c];
+    lv[0].b[i] = a.b_in[c];
     lv[0].x[i] = T(0);
   }
   __syncthreads();
@@ -532,9 +547,14 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
       g_smooth(lv[g], a.pre, true);
       g_residual(lv[g]);
       const GLevel<T>& C = lv[g + 1];
+      const T* r = lv[g].r;
       for (int J = threadIdx.x; J < C.n; J += blockDim.x) {
         T acc = T(0);
-        for (int e = C.child_row[J]; e < C.child_row[J + 1]; ++e) acc += C.child_w[e] * lv[g].r[C.child[e]];
+        for (int w = 0; w < C.CW; ++w) {
+          const size_t o = size_t(w) * C.n + J;
+          const int ch = C.child[o];
+          if (ch >= 0) acc += C.child_w[o] * r[ch];
+        }
         C.b[J] = acc;
         C.x[J] = T(0);
       }
@@ -543,16 +563,17 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
     g_bottom(lv[G - 1], a.bottom_iters, a.w, red);
     for (int g = G - 2; g >= 0; --g) {
       const GLevel<T>& F = lv[g];
-      for (int i = threadIdx.x; i < F.n; i += blockDim.x) F.x[i] += lv[g + 1].x[F.parent[i]];
+      const T* xc = lv[g + 1].x;
+      for (int i = threadIdx.x; i < F.n; i += blockDim.x) F.x[i] += xc[F.parent[i]];
       __syncthreads();
       g_smooth(F, a.post, false);
     }
   }
-  for (int i = threadIdx.x; i < lv[0].n; i += blockDim.x) {
-    const T v = lv[0].x[i];
-    a.x_out[i] = v;
+  for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
+    const T v = lv[0].x[a.perm0[c]];
+    a.x_out[c] = v;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) a.xf_out[(size_t)i * 6 + f] = v;
+    for (int f = 0; f < 6; ++f) a.xf_out[(size_t)c * 6 + f] = v;
   }
 }
 
@@ -584,16 +605,19 @@ static inline int n_wg(int NL, int n_cubes) {
 
 template <typename T>
 hipError_t launch_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s) {
+  if (NL == 16) return launch16_smooth<T>(a, s);
   BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_smooth<NLC, T>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s) {
+  if (NL == 16) return launch16_restrict<T>(a, s);
   BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_restrict<NLC, T>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_apply(int NL, const ApplyArgs<T>& a, hipStream_t s) {
+  if (NL == 16) return launch16_apply<T>(a, s);
   BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_apply<NLC, T>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
   return hipGetLastError();
 }
@@ -604,6 +628,7 @@ hipError_t launch_update(const UpdateArgs<T>& a, hipStream_t s) {
 }
 template <typename TO>
 hipError_t launch_resid64(int NL, const Resid64Args<TO>& a, hipStream_t s) {
+  if (NL == 16) return launch16_resid64<TO>(a, s);
   BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_resid64<NLC, TO>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
   return hipGetLastError();
 }
@@ -628,7 +653,14 @@ hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s) {
 }
 template <typename T>
 hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_mg<T>), dim3(1), dim3(1024), 0, s, a);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_mg<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kGraphLdsBudget);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_coarse_mg<T>), dim3(1), dim3(1024), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_coarse_mg<float>(const CoarseMGArgs<float>&, hipStream_t);

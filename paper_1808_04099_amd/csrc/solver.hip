@@ -82,10 +82,12 @@ struct bcm_plan {
   // cube-graph multigrid (coarse_solver 1)
   bool graph = false;
   struct GOff {
-    size_t row, col, val, diag, vol, order, parent, child_row, child, child_w, x, b, r;
+    size_t col, val, diag, vol, parent, child, child_w, x, b, r;
+    int lds_x, lds_b, lds_r;
   };
   std::vector<GOff> g_off;
-  size_t o_glev = 0, o_gw = 0;
+  size_t o_glev = 0, o_gw = 0, o_perm0 = 0;
+  int g_lds = 0;
   Timer timer;
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
@@ -201,9 +203,9 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
   }
   if (P->graph) {
     CoarseMGArgs<T> ga{B(L - 1), X(L - 1), F(1, L - 1), P->at<const GLevel<T>>(P->o_glev),
-                       int(P->g_off.size()), o.coarse_cycles, 2, 2,
-                       std::max(o.coarse_iters, 64),  // the last graph level has <= 64 nodes
-                       P->at<double>(P->o_gw)};
+                       P->at<const int32_t>(P->o_perm0), int(P->g_off.size()), o.coarse_cycles,
+                       2, 2, std::max(o.coarse_iters, 64),  // the last graph level has <= 64 nodes
+                       P->at<double>(P->o_gw), P->g_lds};
     HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse_mg<T>(ga, s); }), "k_coarse_mg");
   } else {
     CoarseArgs<T> ca{P->at<const CubeMeta>(P->o_meta), P->nc, double(P->n), B(L - 1), X(L - 1),
@@ -249,7 +251,7 @@ template <typename T>
 int krylov(bcm_plan* P, T* x, double thr, int max_iter, double hist_scale, SolveLog& log,
            Scalars* hs, hipStream_t s) {
   const int NL = P->n;
-  const int nparts = n_wg(NL, P->nc);
+  const int nparts = partials_of(NL, P->nc);
   T* r = P->at<T>(P->o_r);
   T* z = P->at<T>(P->o_z);
   T* p = P->at<T>(P->o_p);
@@ -295,7 +297,7 @@ int residual64(bcm_plan* P, const double* p, const double* b, TO* r, double rsca
   Resid64Args<TO> ra{geom(P, NL), p, P->at<const double>(P->o_pf), b, r,
                      P->at<double>(P->o_part[0]), P->at<double>(P->o_part[1]), rscale};
   HIPCHK(timed(P, cls_of("resid64", 0), s, [&] { return launch_resid64<TO>(NL, ra, s); }), "k_resid64");
-  return finalize(P, OP_BB, 0, 1, n_wg(NL, P->nc), 0, s);
+  return finalize(P, OP_BB, 0, 1, partials_of(NL, P->nc), 0, s);
 }
 
 // Solve A p = b to opts.tol (relative, V-weighted, FP64).  p holds the guess if use_guess.
@@ -524,37 +526,37 @@ int upload_graph(bcm_plan* P, hipStream_t s) {
   for (size_t g = 0; g < Ls.size(); ++g) {
     const CoarseLevel& L = Ls[g];
     const bcm_plan::GOff& o = P->g_off[g];
-    HIPCHK(put(o.row, L.row.data(), L.row.size() * 4), "upload graph rows");
-    HIPCHK(put(o.col, L.col.data(), L.col.size() * 4), "upload graph columns");
-    HIPCHK(put(o.val, conv(L.val).data(), L.val.size() * sizeof(T)), "upload graph values");
-    HIPCHK(put(o.diag, conv(L.diag).data(), L.diag.size() * sizeof(T)), "upload graph diagonal");
-    HIPCHK(put(o.vol, conv(L.vol).data(), L.vol.size() * sizeof(T)), "upload graph volumes");
-    HIPCHK(put(o.order, L.order.data(), L.order.size() * 4), "upload graph colouring");
-    HIPCHK(put(o.parent, L.parent.data(), L.parent.size() * 4), "upload graph parents");
+    HIPCHK(put(o.col, L.e_col.data(), L.e_col.size() * 4), "upload graph columns");
+    HIPCHK(put(o.val, conv(L.e_val).data(), L.e_val.size() * sizeof(T)), "upload graph values");
+    HIPCHK(put(o.diag, conv(L.e_diag).data(), L.e_diag.size() * sizeof(T)), "upload graph diagonal");
+    HIPCHK(put(o.vol, conv(L.e_vol).data(), L.e_vol.size() * sizeof(T)), "upload graph volumes");
+    HIPCHK(put(o.parent, L.e_parent.data(), L.e_parent.size() * 4), "upload graph parents");
     if (g > 0) {
-      HIPCHK(put(o.child_row, L.child_row.data(), L.child_row.size() * 4), "upload graph children");
-      HIPCHK(put(o.child, L.child.data(), L.child.size() * 4), "upload graph children");
-      HIPCHK(put(o.child_w, conv(L.child_w).data(), L.child_w.size() * sizeof(T)), "upload graph weights");
+      HIPCHK(put(o.child, L.e_child.data(), L.e_child.size() * 4), "upload graph children");
+      HIPCHK(put(o.child_w, conv(L.e_child_w).data(), L.e_child_w.size() * sizeof(T)), "upload graph weights");
     }
     GLevel<T>& d = lev[g];
     std::memset(&d, 0, sizeof(d));
     d.n = L.n;
     d.ncol = int(L.color_off.size()) - 1;
+    d.W = L.W;
+    d.CW = L.CW;
     for (int c = 0; c <= d.ncol; ++c) d.color_off[c] = L.color_off[c];
-    d.row = P->at<const int32_t>(o.row);
+    d.lds_x = o.lds_x;
+    d.lds_b = o.lds_b;
+    d.lds_r = o.lds_r;
     d.col = P->at<const int32_t>(o.col);
     d.val = P->at<const T>(o.val);
     d.diag = P->at<const T>(o.diag);
     d.vol = P->at<const T>(o.vol);
-    d.order = P->at<const int32_t>(o.order);
-    d.parent = L.parent.empty() ? nullptr : P->at<const int32_t>(o.parent);
-    d.child_row = g > 0 ? P->at<const int32_t>(o.child_row) : nullptr;
+    d.parent = L.e_parent.empty() ? nullptr : P->at<const int32_t>(o.parent);
     d.child = g > 0 ? P->at<const int32_t>(o.child) : nullptr;
     d.child_w = g > 0 ? P->at<const T>(o.child_w) : nullptr;
     d.x = P->at<T>(o.x);
     d.b = P->at<T>(o.b);
     d.r = P->at<T>(o.r);
   }
+  HIPCHK(put(P->o_perm0, Ls[0].perm.data(), Ls[0].perm.size() * 4), "upload graph permutation");
   HIPCHK(put(P->o_glev, lev.data(), lev.size() * sizeof(GLevel<T>)), "upload graph levels");
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   return BCM_OK;
@@ -588,7 +590,7 @@ void bcm_default_opts(bcm_solver_opts* o) {
   o->coarse_iters = 10;
   o->krylov = 1;
   o->coarse_solver = 1;
-  o->coarse_cycles = 2;
+  o->coarse_cycles = 1;
 }
 
 int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan** out,
@@ -664,26 +666,40 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
     for (size_t g = 0; g < Ls.size(); ++g) {
       const CoarseLevel& L = Ls[g];
       bcm_plan::GOff go{};
-      const size_t n = size_t(L.n), nnz = std::max<size_t>(L.col.size(), 1);
-      go.row = take(top, (n + 1) * 4);
-      go.col = take(top, nnz * 4);
-      go.val = take(top, nnz * Ti);
+      const size_t n = size_t(L.n);
+      go.col = take(top, L.e_col.size() * 4);
+      go.val = take(top, L.e_val.size() * Ti);
       go.diag = take(top, n * Ti);
       go.vol = take(top, n * Ti);
-      go.order = take(top, n * 4);
-      go.parent = take(top, std::max<size_t>(L.parent.size(), 1) * 4);
+      go.parent = take(top, std::max<size_t>(L.e_parent.size(), 1) * 4);
       if (g > 0) {
-        go.child_row = take(top, (n + 1) * 4);
-        go.child = take(top, L.child.size() * 4);
-        go.child_w = take(top, L.child.size() * Ti);
+        go.child = take(top, L.e_child.size() * 4);
+        go.child_w = take(top, L.e_child.size() * Ti);
       }
       go.x = take(top, n * Ti);
       go.b = take(top, n * Ti);
       go.r = take(top, n * Ti);
+      go.lds_x = go.lds_b = go.lds_r = -1;
       P->g_off.push_back(go);
     }
+    // LDS placement, smallest levels first: x, then b and r, while the budget lasts
+    int lds = 0;
+    auto place = [&](int& slot, size_t n) {
+      const int bytes = int((n * Ti + 15) / 16 * 16);
+      if (lds + bytes <= kGraphLdsBudget) {
+        slot = lds;
+        lds += bytes;
+      }
+    };
+    for (int g = int(Ls.size()) - 1; g >= 0; --g) place(P->g_off[g].lds_x, Ls[g].n);
+    for (int g = int(Ls.size()) - 1; g >= 0; --g) {
+      place(P->g_off[g].lds_b, Ls[g].n);
+      place(P->g_off[g].lds_r, Ls[g].n);
+    }
+    P->g_lds = lds;
     P->o_glev = take(top, Ls.size() * sizeof(GLevel<double>));
     P->o_gw = take(top, 4 * size_t(Ls.back().n) * sizeof(double));
+    P->o_perm0 = take(top, Ls[0].perm.size() * 4);
   }
   P->ws_bytes = top;
   if (workspace_bytes) *workspace_bytes = top;
