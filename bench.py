@@ -156,6 +156,7 @@ def run(args):
     log(f"[bench] {prec}: {ms:.2f} ms/step, {rep.n_inner} inner its, {rep.n_outer} outer, "
         f"rel.res {rep.final_rel_res:.2e}; {dominant}: {avg_ms:.3f} ms/launch, "
         f"{achieved:.0f} GB/s")
+    log("[bench] residual history: " + " ".join(f"{v:.1e}" for v in rep.history))
     result = {
         "metric": "Poisson cell-updates/s (mixed-precision projection to 1e-10)",
         "value": value,

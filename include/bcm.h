@@ -100,7 +100,9 @@ typedef struct {
   double tol;           /* target ||b - A p||_V / ||b||_V, evaluated in FP64       [1e-10] */
   int32_t max_iter;     /* Krylov iterations per solve (FP64 mode) / per inner solve   [50] */
   int32_t max_outer;    /* mixed modes: FP64 refinement steps                          [10] */
-  double inner_tol;     /* mixed modes: relative tolerance of each FP32 inner solve  [1e-6] */
+  double inner_tol;     /* mixed modes: residual reduction asked of each FP32 inner solve
+                           (the last one only as much as tol still needs); FP32 rounding
+                           of the operator limits what one refinement step gains   [1e-3] */
   int32_t pre_sweeps;   /* red-black Gauss-Seidel sweeps before restriction             [2] */
   int32_t post_sweeps;  /* sweeps after prolongation                                    [2] */
   int32_t coarse_iters; /* CG iterations on the one-cell-per-cube level (coarse_solver 0),

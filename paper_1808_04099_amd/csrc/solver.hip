@@ -584,7 +584,7 @@ void bcm_default_opts(bcm_solver_opts* o) {
   o->tol = 1e-10;
   o->max_iter = 50;
   o->max_outer = 10;
-  o->inner_tol = 1e-6;
+  o->inner_tol = 1e-3;
   o->pre_sweeps = 2;
   o->post_sweeps = 2;
   o->coarse_iters = 10;
