@@ -17,6 +17,7 @@ struct Geom {  // what every cube-tiled kernel needs
   const int32_t* launch;
   int n_cubes;
   double hscale;  // cell width at this level = meta.h * hscale
+  int multilevel; // the mesh has 2:1 faces (a face may need four neighbour values)
 };
 
 template <typename T>
@@ -214,6 +215,9 @@ template <typename T> hipError_t launch16_smooth(const SmoothArgs<T>& a, hipStre
 template <typename T> hipError_t launch16_restrict(const RestrictArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch16_apply(const ApplyArgs<T>& a, hipStream_t s);
 template <typename TO> hipError_t launch16_resid64(const Resid64Args<TO>& a, hipStream_t s);
+template <typename TF> hipError_t launch16_force(const ForceArgs<TF>& a, hipStream_t s);
+template <typename TF> hipError_t launch16_div(const DivArgs<TF>& a, hipStream_t s);
+template <typename TF> hipError_t launch16_correct(const CorrectArgs<TF>& a, hipStream_t s);
 
 // Number of partial sums a tiled kernel at level NL writes.
 inline int partials_of(int NL, int n_cubes);

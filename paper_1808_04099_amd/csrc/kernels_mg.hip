@@ -455,22 +455,65 @@ __device__ __forceinline__ T g_offdiag(const GLevel<T>& L, const T* x, int i) {
   return acc;
 }
 
+// Width-6 rows (every lattice level): four nodes per lane per pass, all their coupling loads
+// issued before any of them is used.
+template <typename T, bool RESID>
+__device__ __forceinline__ void g_pass6(const GLevel<T>& L, int lo, int hi) {
+  constexpr int U = 4;
+  for (int base = lo + threadIdx.x; base < hi; base += U * 1024) {
+    int col[U][6];
+    T val[U][6], bb[U], dg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * 1024;
+      const int ii = i < hi ? i : lo;
+#pragma unroll
+      for (int w = 0; w < 6; ++w) {
+        col[u][w] = L.col[size_t(w) * L.n + ii];
+        val[u][w] = L.val[size_t(w) * L.n + ii];
+      }
+      bb[u] = L.b[ii];
+      dg[u] = L.diag[ii];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * 1024;
+      if (i >= hi) continue;
+      T acc = T(0);
+#pragma unroll
+      for (int w = 0; w < 6; ++w) acc += val[u][w] * L.x[col[u][w]];
+      if (RESID)
+        L.r[i] = bb[u] - dg[u] * L.x[i] - acc;
+      else
+        L.x[i] = (bb[u] - acc) / dg[u];
+    }
+  }
+}
+
 template <typename T>
 __device__ void g_smooth(const GLevel<T>& L, int sweeps, bool forward) {
   for (int s = 0; s < sweeps; ++s)
     for (int cc = 0; cc < L.ncol; ++cc) {
       const int c = forward ? cc : L.ncol - 1 - cc;
       const int o1 = L.color_off[c + 1];
-      for (int i = L.color_off[c] + threadIdx.x; i < o1; i += blockDim.x)
-        L.x[i] = (L.b[i] - g_offdiag(L, L.x, i)) / L.diag[i];
+      if (L.W == 6) {
+        g_pass6<T, false>(L, L.color_off[c], o1);
+      } else {
+        for (int i = L.color_off[c] + threadIdx.x; i < o1; i += blockDim.x)
+          L.x[i] = (L.b[i] - g_offdiag(L, L.x, i)) / L.diag[i];
+      }
       __syncthreads();
     }
 }
 
 template <typename T>
 __device__ void g_residual(const GLevel<T>& L) {
-  for (int i = threadIdx.x; i < L.n; i += blockDim.x)
-    L.r[i] = L.b[i] - L.diag[i] * L.x[i] - g_offdiag(L, L.x, i);
+  if (L.W == 6) {
+    g_pass6<T, true>(L, 0, L.n);
+  } else {
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x)
+      L.r[i] = L.b[i] - L.diag[i] * L.x[i] - g_offdiag(L, L.x, i);
+  }
   __syncthreads();
 }
 

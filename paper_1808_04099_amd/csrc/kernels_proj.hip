@@ -340,16 +340,19 @@ static inline int n_wg(int NL, int n_cubes) {
 
 template <typename TF>
 hipError_t launch_force(int NL, const ForceArgs<TF>& a, hipStream_t s) {
+  if (NL == 16) return launch16_force<TF>(a, s);
   BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_force<NLC, TF>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
   return hipGetLastError();
 }
 template <typename TF>
 hipError_t launch_div(int NL, const DivArgs<TF>& a, hipStream_t s) {
+  if (NL == 16 && !a.part_bb) return launch16_div<TF>(a, s);
   BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_div<NLC, TF>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
   return hipGetLastError();
 }
 template <typename TF>
 hipError_t launch_correct(int NL, const CorrectArgs<TF>& a, hipStream_t s) {
+  if (NL == 16 && !a.face_u[0] && !a.face_u[1] && !a.face_u[2]) return launch16_correct<TF>(a, s);
   BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_correct<NLC, TF>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
   return hipGetLastError();
 }

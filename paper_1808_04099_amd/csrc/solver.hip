@@ -148,7 +148,7 @@ int cls_of(const char* base, int NL) {
 
 Geom geom(const bcm_plan* P, int NL) {
   return Geom{P->at<const CubeMeta>(P->o_meta), P->at<const int32_t>(P->o_launch), P->nc,
-              double(P->n) / double(NL)};
+              double(P->n) / double(NL), P->M->multilevel ? 1 : 0};
 }
 
 int read_scalars(bcm_plan* P, Scalars* host, hipStream_t s) {
@@ -286,11 +286,13 @@ int krylov(bcm_plan* P, T* x, double thr, int max_iter, double hist_scale, Solve
   return BCM_OK;
 }
 
-// True FP64 residual of p (faces exported first): <r,r>_V (and <b,b>_V) into the scalars.
+// True FP64 residual of p (faces exported first unless they are current): <r,r>_V (and
+// <b,b>_V) into the scalars.
 template <typename TO>
-int residual64(bcm_plan* P, const double* p, const double* b, TO* r, double rscale, hipStream_t s) {
+int residual64(bcm_plan* P, const double* p, const double* b, TO* r, double rscale, hipStream_t s,
+               bool faces_current = false) {
   const int NL = P->n;
-  if (p) {
+  if (p && !faces_current) {
     int st = export64(P, const_cast<double*>(p), P->at<double>(P->o_pf), s);
     if (st) return st;
   }
@@ -308,6 +310,7 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
   Scalars hs{};
   int st = BCM_OK;
   int outer = 0;
+  bool faces_ok = false;  // the face buffer holds the faces of the current p
   if (!use_guess) HIPCHK(fill<double>(p, P->cells, s), "zero fill");
   double bb = 0.0, rr = 0.0;
   const double tol2 = o.tol * o.tol;
@@ -347,7 +350,9 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
     double rscale = 1.0;
     for (outer = 0; outer < o.max_outer; ++outer) {
       float* r32 = P->at<float>(P->o_r);
-      if ((st = residual64<float>(P, (use_guess || outer) ? p : nullptr, b, r32, rscale, s))) return st;
+      const double* pg = (use_guess || outer) ? p : nullptr;
+      if ((st = residual64<float>(P, pg, b, r32, rscale, s, faces_ok))) return st;
+      faces_ok = pg != nullptr;
       if ((st = read_scalars(P, &hs, s))) return st;
       if (outer == 0) bb = hs.bb;
       rr = hs.rr;
@@ -356,6 +361,8 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
         return BCM_ERR_NONFINITE;
       }
       if (bb == 0.0) {
+        HIPCHK(fill<double>(p, P->cells, s), "zero fill");
+        faces_ok = false;
         rr = 0.0;
         converged = true;
         break;
@@ -368,7 +375,7 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
       if (outer == 0 && !(rscale > 0 && std::fabs(std::log10(rr / vol)) < 20)) {
         // first pass unscaled and far from unit size: redo the conversion with the true norm
         rscale = 1.0 / std::sqrt(rr / vol);
-        if ((st = residual64<float>(P, use_guess ? p : nullptr, b, r32, rscale, s))) return st;
+        if ((st = residual64<float>(P, pg, b, r32, rscale, s, faces_ok))) return st;
       }
       float* d = P->at<float>(P->o_d);
       HIPCHK(fill<float>(d, P->cells, s), "zero fill");
@@ -381,6 +388,7 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
         return st;
       IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale};
       HIPCHK(timed(P, cls_of("ir", 0), s, [&] { return launch_ir<float>(P->n, ia, s); }), "k_ir");
+      faces_ok = true;  // k_ir exports the faces of the updated p
       const double rr_est = hs.rr / (rscale * rscale);
       if (rr_est > 0 && std::isfinite(rr_est)) rscale = 1.0 / std::sqrt(rr_est / vol);
     }
@@ -392,7 +400,7 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
     rep->status = converged ? BCM_OK : BCM_NOT_CONVERGED;
   }
   // leave the faces of p exported for the correction kernels
-  if ((st = export64(P, p, P->at<double>(P->o_pf), s))) return st;
+  if (!faces_ok && (st = export64(P, p, P->at<double>(P->o_pf), s))) return st;
   return converged ? BCM_OK : BCM_NOT_CONVERGED;
 }
 
