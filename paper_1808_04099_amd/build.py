@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libbcm.so")
-SOURCES = ["mesh.cpp", "coarse.cpp", "kernels_mg.hip", "kernels_fine.hip", "kernels_proj.hip",
+SOURCES = ["mesh.cpp", "coarse.cpp", "kernels_mg.hip", "kernels_col.hip", "kernels_proj.hip",
            "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -131,6 +131,52 @@ void build_level(CoarseLevel& L, const std::vector<Key>& keys, const int dims[3]
 
 }  // namespace
 
+// Inverse of the operator of a small level in its device node order (row i: diag_i x_i +
+// sum_w val_wi x_col_wi), stored transposed (inv[j * n + i] = (M^-1)_ij) so that the lanes
+// that compute consecutive rows read consecutive values.  Gauss-Jordan with partial
+// pivoting; empty when the level is too large or the operator is numerically singular.
+static std::vector<double> dense_inverse_transposed(const CoarseLevel& L) {
+  const int n = L.n;
+  if (n <= 0 || n > kBottomDirectMax) return {};
+  std::vector<double> a(size_t(n) * n, 0.0), inv(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    a[size_t(i) * n + i] += L.e_diag[i];
+    for (int w = 0; w < L.W; ++w) a[size_t(i) * n + L.e_col[size_t(w) * n + i]] += L.e_val[size_t(w) * n + i];
+    inv[size_t(i) * n + i] = 1.0;
+  }
+  double scale = 0.0;
+  for (double v : a) scale = std::max(scale, std::fabs(v));
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[size_t(r) * n + c]) > std::fabs(a[size_t(piv) * n + c])) piv = r;
+    if (!(std::fabs(a[size_t(piv) * n + c]) > 1e-12 * scale)) return {};
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[size_t(piv) * n + k], a[size_t(c) * n + k]);
+        std::swap(inv[size_t(piv) * n + k], inv[size_t(c) * n + k]);
+      }
+    const double d = 1.0 / a[size_t(c) * n + c];
+    for (int k = 0; k < n; ++k) {
+      a[size_t(c) * n + k] *= d;
+      inv[size_t(c) * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[size_t(r) * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        a[size_t(r) * n + k] -= f * a[size_t(c) * n + k];
+        inv[size_t(r) * n + k] -= f * inv[size_t(c) * n + k];
+      }
+    }
+  }
+  std::vector<double> t(size_t(n) * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) t[size_t(j) * n + i] = inv[size_t(i) * n + j];
+  return t;
+}
+
 bool build_coarse_hierarchy(const HostMesh& M, CoarseHierarchy& H, int max_levels) {
   H.levels.clear();
   H.ok = false;
@@ -285,6 +331,7 @@ bool build_coarse_hierarchy(const HostMesh& M, CoarseHierarchy& H, int max_level
     }
     if (g == 0) L.perm = id;
   }
+  H.bottom_inv = dense_inverse_transposed(H.levels.back());
   H.ok = true;
   return true;
 }

@@ -30,9 +30,13 @@ struct CoarseLevel {
   std::vector<int32_t> perm;          // level 0: perm[cube] = device node index
 };
 
+// The last graph level is solved directly (dense inverse) when it has at most this many nodes.
+constexpr int kBottomDirectMax = 64;
+
 struct CoarseHierarchy {
   bool ok = false;
   std::vector<CoarseLevel> levels;    // levels[0] = the one-cell-per-cube graph
+  std::vector<double> bottom_inv;     // [n][n] transposed inverse of the last level, or empty
 };
 
 bool build_coarse_hierarchy(const HostMesh& M, CoarseHierarchy& H, int max_levels);
@@ -68,6 +72,7 @@ struct CoarseMGArgs {
   int nlev;
   int cycles, pre, post, bottom_iters;
   double* w;                // CG work space for the bottom level (4 * n_last doubles)
+  const T* binv;            // transposed inverse of the bottom operator, or nullptr (CG)
   int lds_bytes;            // dynamic LDS the launch reserves for the lds_* placements
 };
 

@@ -208,29 +208,30 @@ template <typename TF> hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s);
 
-// Persistent 16^3 kernels (kernels_fine.hip).  Their grid never exceeds fine_grid(n_cubes);
-// they write fine_grid(n_cubes) partial sums (zeros past their own grid).
-__host__ __device__ inline int fine_grid(int n_cubes) { return n_cubes < 4096 ? n_cubes : 4096; }
-template <typename T> hipError_t launch16_smooth(const SmoothArgs<T>& a, hipStream_t s);
-template <typename T> hipError_t launch16_restrict(const RestrictArgs<T>& a, hipStream_t s);
-template <typename T> hipError_t launch16_apply(const ApplyArgs<T>& a, hipStream_t s);
-template <typename TO> hipError_t launch16_resid64(const Resid64Args<TO>& a, hipStream_t s);
+// Persistent column kernels of the per-cube levels (kernels_col.hip).  A workgroup handles
+// units of col_cpb(NL) cubes; the grid never exceeds fine_grid(units) workgroups, and the
+// kernels that reduce write fine_grid(units) partial sums (zeros past their own grid).
+__host__ __device__ inline int fine_grid(int units) { return units < 4096 ? units : 4096; }
+__host__ __device__ inline int col_cpb(int NL) { return NL >= 16 ? 1 : 256 / (NL * NL); }
+__host__ __device__ inline int col_units(int cpb, int n_cubes) {
+  return cpb == 1 ? n_cubes : 8 * ((n_cubes + 8 * cpb - 1) / (8 * cpb));
+}
+template <typename T> hipError_t launchc_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launchc_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launchc_apply(int NL, const ApplyArgs<T>& a, hipStream_t s);
+template <typename TO> hipError_t launchc_resid64(int NL, const Resid64Args<TO>& a, hipStream_t s);
+template <typename T> hipError_t launchc_ir(int NL, const IrArgs<T>& a, hipStream_t s);
 template <typename TF> hipError_t launch16_force(const ForceArgs<TF>& a, hipStream_t s);
 template <typename TF> hipError_t launch16_div(const DivArgs<TF>& a, hipStream_t s);
 template <typename TF> hipError_t launch16_correct(const CorrectArgs<TF>& a, hipStream_t s);
 
-// Number of partial sums a tiled kernel at level NL writes.
-inline int partials_of(int NL, int n_cubes);
+// Number of partial sums a column kernel at level NL writes.
+inline int partials_of(int NL, int n_cubes) { return fine_grid(col_units(col_cpb(NL), n_cubes)); }
 
+// Cubes per workgroup of the LDS-tile kernels (tile.hpp).
 inline int cubes_per_wg(int NL) {
   const int n3 = NL * NL * NL;
   return n3 >= 256 ? 1 : 256 / n3;
-}
-
-inline int partials_of(int NL, int n_cubes) {
-  if (NL == 16) return fine_grid(n_cubes);
-  const int c = cubes_per_wg(NL);
-  return (n_cubes + c - 1) / c;
 }
 
 }  // namespace bcm

@@ -1,0 +1,876 @@
+// Column kernels of the per-cube multigrid levels (16^3, 8^3, 4^3, 2^3 cells per cube): the
+// HBM-bound part of the Poisson solve, plus the 16^3 projection kernels.
+//
+// Layout per workgroup (256 lanes): lane t owns one column (i, j) of a cube, k = 0..NL-1 held
+// in registers; a workgroup holds CPB = max(1, 256 / NL^2) cubes.  Only the i/j neighbours go
+// through LDS: per cube a tile of NL planes of (NL+2) x (NL+2) (the plane plus its x/y halo
+// ring); the z neighbours are the lane's own registers, with the z halo of the column in two
+// registers.  Every global access is a full plane of a cube (coalesced) or a face slab.
+//
+// The solver kernels are persistent: a workgroup walks units of CPB cubes with stride
+// gridDim.x (a multiple of 8, so each workgroup stays on the XCD that owns its stretch of the
+// Z-ordered launch table) and, while it computes one unit, the loads of its next unit are in
+// flight.  The prefetch does integer work only: the halo addresses are computed branch-free
+// from the face relations and the loads land in raw registers that are combined when the cube
+// is staged, because any arithmetic on a loaded value makes the in-order load counter wait
+// for every load issued before it (the prefetched columns included).
+#include <algorithm>
+
+#include "kernels.hpp"
+#include "tile.hpp"
+
+namespace bcm {
+
+namespace {
+
+template <int NL>
+struct Col {
+  static constexpr int N2 = NL * NL, N3 = N2 * NL;
+  static constexpr int CPB = NL >= 16 ? 1 : 256 / N2;  // cubes per workgroup
+  static constexpr int W = NL + 2, P = W * W, TS = NL * P;  // LDS tile of one cube
+  static constexpr int H = NL / 2, H2 = H * H, H3 = H2 * H;  // next coarser per-cube level
+  static constexpr int F = 6 * N2, FH = 6 * H2;  // face-buffer values per cube (this level, next)
+  __device__ static int tix(int s, int i, int j, int k) { return s * TS + k * P + (j + 1) * W + (i + 1); }
+  // LDS position of the halo cell of face f (0..3) at tangential position (t1, t2)
+  __device__ static int halo(int s, int f, int t1, int t2) {
+    switch (f) {
+      case 0: return tix(s, -1, t1, t2);
+      case 1: return tix(s, NL, t1, t2);
+      case 2: return tix(s, t1, -1, t2);
+      default: return tix(s, t1, NL, t2);
+    }
+  }
+};
+
+// Lane geometry: cube slot s of the workgroup and column (i, j) within that cube.
+template <int NL>
+struct LaneC {
+  int s, l, i, j;
+  __device__ explicit LaneC(int t) {
+    s = t / Col<NL>::N2;
+    l = t - s * Col<NL>::N2;
+    i = l % NL;
+    j = l / NL;
+  }
+};
+
+// Cube of slot s of unit u (-1 past the end).  With several cubes per unit, the unit takes
+// launch-table positions 8 apart, so that all of them come from the stretch of the table that
+// belongs to the unit's XCD (unit u runs on XCD u mod 8 when the grid is a multiple of 8).
+template <int NL>
+__device__ __forceinline__ int unit_cube(const Geom& g, int u, int s) {
+  constexpr int CPB = Col<NL>::CPB;
+  const int p = CPB == 1 ? u : ((u >> 3) * CPB + s) * 8 + (u & 7);
+  int c = p < g.n_cubes ? g.launch[p] : -1;
+  if (Col<NL>::N2 >= 64) c = __builtin_amdgcn_readfirstlane(c);  // one cube per wavefront
+  return c;
+}
+
+// Face-buffer offsets of the NQ neighbour values a lane needs on each face (NQ = 1 on
+// single-level meshes, 4 where a face may be covered by four finer cubes).  Same-level and
+// coarser faces repeat one address; domain-boundary faces point at the cube's own slab (a
+// value that staging discards).  Offsets into the face buffer of this level and, for
+// prolongated corrections, into that of the next coarser level.
+template <int NQ>
+struct Slots {
+  int fine[6][NQ];
+  int coarse[6][NQ];
+  int kind[6];
+};
+
+template <int NL, int NQ>
+__device__ __forceinline__ void slots(const CubeMeta& m, int self, int t1, int t2, Slots<NQ>& S,
+                                      bool coarse) {
+  using C = Col<NL>;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int kd = m.kind[f], of = f ^ 1;
+    S.kind[f] = kd;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      int c = self, o = f, a = t1, b = t2;
+      if (kd == FK_SAME) {
+        c = m.nbr[f][0];
+        o = of;
+      } else if (kd == FK_COARSER) {
+        const int qd = m.quad[f];
+        c = m.nbr[f][0];
+        o = of;
+        a = (qd & 1) * C::H + (t1 >> 1);
+        b = (qd >> 1) * C::H + (t2 >> 1);
+      } else if (kd == FK_FINER) {
+        const int F1 = 2 * t1 + (q & 1), F2 = 2 * t2 + (q >> 1);
+        c = m.nbr[f][(F1 / NL) + 2 * (F2 / NL)];
+        o = of;
+        a = F1 % NL;
+        b = F2 % NL;
+      }
+      S.fine[f][q] = c * C::F + o * C::N2 + b * NL + a;
+      if (coarse) S.coarse[f][q] = c * C::FH + o * C::H2 + (b >> 1) * C::H + (a >> 1);
+    }
+  }
+}
+
+// Scaled halo value of one face from its raw neighbour values (RULE_P).  A select, not a zero
+// scale: the dummy slab of a boundary face may hold anything.
+template <typename T, int NQ>
+__device__ __forceinline__ T halo_val(int kd, const T (&r)[NQ]) {
+  T s = r[0];
+  if (NQ == 4 && kd == FK_FINER) s = T(0.25) * (((r[0] + r[1]) + r[2]) + r[3]);
+  return kd <= FK_FINER ? T(RuleTab<RULE_P>::nbeff(kd)) * s : T(0);
+}
+
+// Stage face values: faces 0..3 into the LDS ring at this lane's slot, 4/5 into registers.
+template <int NL, typename T>
+__device__ __forceinline__ void stage(T* tile, const T (&hv)[6], const LaneC<NL>& L, T& zlo, T& zhi) {
+#pragma unroll
+  for (int f = 0; f < 4; ++f) tile[Col<NL>::halo(L.s, f, L.i, L.j)] = hv[f];
+  zlo = hv[4];
+  zhi = hv[5];
+}
+
+// Diagonal (sum of own coefficients) of the lane's column: cells k = 0, 1..NL-2, NL-1.
+template <int NL, typename T>
+__device__ __forceinline__ void diag(const CubeMeta& m, int i, int j, T& d0, T& dm, T& dl) {
+  T c = T(6);
+  if (i == 0) c += T(RuleTab<RULE_P>::own(m.kind[0])) - T(1);
+  if (i == NL - 1) c += T(RuleTab<RULE_P>::own(m.kind[1])) - T(1);
+  if (j == 0) c += T(RuleTab<RULE_P>::own(m.kind[2])) - T(1);
+  if (j == NL - 1) c += T(RuleTab<RULE_P>::own(m.kind[3])) - T(1);
+  dm = c;
+  d0 = c + T(RuleTab<RULE_P>::own(m.kind[4])) - T(1);
+  dl = c + T(RuleTab<RULE_P>::own(m.kind[5])) - T(1);
+}
+
+// Write the six face slabs of a cube from the lane's column.
+template <int NL, typename T>
+__device__ __forceinline__ void export_col(T* xf, int c, const T (&x)[NL], int i, int j) {
+  constexpr int N2 = Col<NL>::N2;
+  T* base = xf + (size_t)c * Col<NL>::F;
+  if (i == 0)
+#pragma unroll
+    for (int k = 0; k < NL; ++k) base[0 * N2 + k * NL + j] = x[k];
+  if (i == NL - 1)
+#pragma unroll
+    for (int k = 0; k < NL; ++k) base[1 * N2 + k * NL + j] = x[k];
+  if (j == 0)
+#pragma unroll
+    for (int k = 0; k < NL; ++k) base[2 * N2 + k * NL + i] = x[k];
+  if (j == NL - 1)
+#pragma unroll
+    for (int k = 0; k < NL; ++k) base[3 * N2 + k * NL + i] = x[k];
+  base[4 * N2 + j * NL + i] = x[0];
+  base[5 * N2 + j * NL + i] = x[NL - 1];
+}
+
+template <int NL, typename T>
+__device__ __forceinline__ T nbsum(const T* tile, const T (&x)[NL], int k, int c, T zlo, T zhi) {
+  constexpr int W = Col<NL>::W;
+  const T zm = k > 0 ? x[k > 0 ? k - 1 : 0] : zlo;
+  const T zp = k < NL - 1 ? x[k < NL - 1 ? k + 1 : NL - 1] : zhi;
+  return tile[c - 1] + tile[c + 1] + tile[c - W] + tile[c + W] + zm + zp;
+}
+
+// Zero the partial sums past the grid, up to the count the reduction reads.
+__device__ __forceinline__ void zero_tail(double* part, int units) {
+  for (int k = blockIdx.x + gridDim.x; k < fine_grid(units); k += gridDim.x) part[k] = 0.0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Smoother (red-black Gauss-Seidel): POST = prolongation of the coarse correction + smoothing
+// in black-red order (+ fused <x, b> and <x, q> on the finest level), else smoothing in
+// red-black order from a zero initial guess.
+// ------------------------------------------------------------------------------------------
+template <typename T, int NL, bool POST, int NQ>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
+  using C = Col<NL>;
+  __shared__ T tile[C::CPB * C::TS];
+  __shared__ double red[8];
+  const int t = threadIdx.x;
+  const LaneC<NL> L(t);
+  const int i = L.i, j = L.j;
+  const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
+  const bool dots = POST && a.part_zr != nullptr;
+  T nx[NL], nb[NL], nxc[C::H], rf[6][NQ], rc[6][NQ];
+  int kinds[6];
+  auto fetch = [&](int cc) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
+      nb[k] = a.b[g];
+      if (POST) nx[k] = a.x[g];
+    }
+    if (POST) {
+#pragma unroll
+      for (int kk = 0; kk < C::H; ++kk)
+        nxc[kk] = a.xc[(size_t)cc * C::H3 + (kk * C::H + (j >> 1)) * C::H + (i >> 1)];
+      Slots<NQ> S;
+      slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, true);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        kinds[f] = S.kind[f];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          rf[f][q] = a.xf_in[S.fine[f][q]];
+          rc[f][q] = a.xcf[S.coarse[f][q]];
+        }
+      }
+    }
+  };
+  int u = blockIdx.x;
+  int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
+  if (u < U) fetch(c < 0 ? 0 : c);
+  double zr = 0.0, zq = 0.0;
+  while (u < U) {
+    const int ce = c < 0 ? 0 : c;
+    T x[NL], bv[NL];
+    T zlo = T(0), zhi = T(0);
+    const CubeMeta& m = a.g.meta[ce];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      x[k] = POST ? nx[k] + nxc[k >> 1] : T(0);
+      bv[k] = nb[k];
+      tile[C::tix(L.s, i, j, k)] = x[k];
+    }
+    if (POST) {
+      T hv[6];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        T r[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) r[q] = rf[f][q] + rc[f][q];
+        hv[f] = halo_val<T, NQ>(kinds[f], r);
+      }
+      stage<NL, T>(tile, hv, L, zlo, zhi);
+    } else {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) tile[C::halo(L.s, f, i, j)] = T(0);
+    }
+    const T h = T(m.h * a.g.hscale);
+    const T h2 = h * h;
+    T d0, dm, dl;
+    diag<NL, T>(m, i, j, d0, dm, dl);
+    const T i0 = T(1) / d0, im = T(1) / dm, il = T(1) / dl;
+    const double vol = m.vol;
+    const int un = u + G;
+    const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
+    __syncthreads();
+    if (un < U) fetch(cn < 0 ? 0 : cn);
+    // q of this cube for the fused <x, q> (loads overlap the sweeps)
+    T q[NL];
+    if (dots && a.q_dot) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) q[k] = a.q_dot[(size_t)ce * C::N3 + k * C::N2 + L.l];
+    }
+    for (int sw = 0; sw < a.sweeps; ++sw) {
+#pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        const int colour = POST ? (col ^ 1) : col;  // pre: red first, post: black first
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+          if (((i + j + k) & 1) != colour) continue;
+          const int cc = C::tix(L.s, i, j, k);
+          const T sum = nbsum<NL, T>(tile, x, k, cc, zlo, zhi);
+          const T id = k == 0 ? i0 : (k == NL - 1 ? il : im);
+          x[k] = (sum - h2 * bv[k]) * id;
+          tile[cc] = x[k];
+        }
+        __syncthreads();
+      }
+    }
+    if (c >= 0) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        a.x[(size_t)c * C::N3 + k * C::N2 + L.l] = x[k];
+        if (dots) {
+          zr += vol * double(x[k]) * double(bv[k]);
+          if (a.q_dot) zq += vol * double(x[k]) * double(q[k]);
+        }
+      }
+      export_col<NL, T>(a.xf_out, c, x, i, j);
+    }
+    u = un;
+    c = cn;
+  }
+  if (dots) {
+    const double t0 = block_sum(zr, red);
+    __syncthreads();
+    const double t1 = block_sum(zq, red);
+    if (threadIdx.x == 0) {
+      a.part_zr[blockIdx.x] = t0;
+      zero_tail(a.part_zr, U);
+      if (a.part_zq) {
+        a.part_zq[blockIdx.x] = t1;
+        zero_tail(a.part_zq, U);
+      }
+    }
+  }
+}
+
+// Residual of x and restriction to the next level (mean of the 8 children).
+template <typename T, int NL, int NQ>
+__global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
+  using C = Col<NL>;
+  __shared__ T tile[C::CPB * C::TS];
+  __shared__ T rsum[C::CPB * C::H * C::N2];  // residual summed over k pairs, per (slot, kk, j, i)
+  const int t = threadIdx.x;
+  const LaneC<NL> L(t);
+  const int i = L.i, j = L.j;
+  const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
+  T nx[NL], nb[NL], rf[6][NQ];
+  int kinds[6];
+  auto fetch = [&](int cc) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
+      nx[k] = a.x[g];
+      nb[k] = a.b[g];
+    }
+    Slots<NQ> S;
+    slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      kinds[f] = S.kind[f];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) rf[f][q] = a.xf[S.fine[f][q]];
+    }
+  };
+  int u = blockIdx.x;
+  int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
+  if (u < U) fetch(c < 0 ? 0 : c);
+  while (u < U) {
+    const int ce = c < 0 ? 0 : c;
+    T x[NL], bv[NL], hv[6];
+    T zlo, zhi;
+    const CubeMeta& m = a.g.meta[ce];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      x[k] = nx[k];
+      bv[k] = nb[k];
+      tile[C::tix(L.s, i, j, k)] = x[k];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) hv[f] = halo_val<T, NQ>(kinds[f], rf[f]);
+    stage<NL, T>(tile, hv, L, zlo, zhi);
+    const T h = T(m.h * a.g.hscale);
+    const T ih2 = T(1) / (h * h);
+    T d0, dm, dl;
+    diag<NL, T>(m, i, j, d0, dm, dl);
+    const int un = u + G;
+    const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
+    __syncthreads();
+    if (un < U) fetch(cn < 0 ? 0 : cn);
+#pragma unroll
+    for (int kk = 0; kk < C::H; ++kk) {
+      T acc = T(0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = 2 * kk + q;
+        const T d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
+        const T sum = nbsum<NL, T>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
+        acc += bv[k] - (sum - d * x[k]) * ih2;
+      }
+      rsum[(L.s * C::H + kk) * C::N2 + L.l] = acc;
+    }
+    __syncthreads();
+    // coarse cells of the unit: sum the 2x2 (i, j) neighbours of each k-pair sum
+    for (int e = t; e < C::CPB * C::H3; e += 256) {
+      const int s2 = e / C::H3, le = e - s2 * C::H3;
+      const int I = le % C::H, J = (le / C::H) % C::H, K = le / C::H2;
+      const int base = (s2 * C::H + K) * C::N2 + 2 * J * NL + 2 * I;
+      const T sum = rsum[base] + rsum[base + 1] + rsum[base + NL] + rsum[base + NL + 1];
+      const int c2 = unit_cube<NL>(a.g, u, s2);
+      if (c2 >= 0) a.bc[(size_t)c2 * C::H3 + le] = sum * T(0.125);
+    }
+    __syncthreads();
+    u = un;
+    c = cn;
+  }
+}
+
+// p = z + beta p (or z); q = A p; partial <p, q>_V.
+template <typename T, int NL, int NQ>
+__global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
+  using C = Col<NL>;
+  __shared__ T tile[C::CPB * C::TS];
+  __shared__ double red[8];
+  const int t = threadIdx.x;
+  const LaneC<NL> L(t);
+  const int i = L.i, j = L.j;
+  const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
+  const T beta = a.first ? T(0) : T(a.sc->beta);
+  T nz[NL], np[NL], rz[6][NQ], rp[6][NQ];
+  int kinds[6];
+  auto fetch = [&](int cc) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
+      nz[k] = a.z[g];
+      np[k] = a.first ? T(0) : a.p[g];
+    }
+    Slots<NQ> S;
+    slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      kinds[f] = S.kind[f];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        rz[f][q] = a.zf[S.fine[f][q]];
+        rp[f][q] = a.first ? T(0) : a.pf_in[S.fine[f][q]];
+      }
+    }
+  };
+  int u = blockIdx.x;
+  int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
+  if (u < U) fetch(c < 0 ? 0 : c);
+  double pq = 0.0;
+  while (u < U) {
+    const int ce = c < 0 ? 0 : c;
+    T x[NL], hv[6];
+    T zlo, zhi;
+    const CubeMeta& m = a.g.meta[ce];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      x[k] = nz[k] + beta * np[k];
+      tile[C::tix(L.s, i, j, k)] = x[k];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      T r[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) r[q] = rz[f][q] + beta * rp[f][q];
+      hv[f] = halo_val<T, NQ>(kinds[f], r);
+    }
+    stage<NL, T>(tile, hv, L, zlo, zhi);
+    const T h = T(m.h * a.g.hscale);
+    const T ih2 = T(1) / (h * h);
+    T d0, dm, dl;
+    diag<NL, T>(m, i, j, d0, dm, dl);
+    const double vol = m.vol;
+    const int un = u + G;
+    const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
+    __syncthreads();
+    if (un < U) fetch(cn < 0 ? 0 : cn);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const T d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
+      const T sum = nbsum<NL, T>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
+      const T qv = (sum - d * x[k]) * ih2;
+      if (c >= 0) {
+        const size_t g = (size_t)c * C::N3 + k * C::N2 + L.l;
+        a.p[g] = x[k];
+        a.q[g] = qv;
+        pq += vol * double(x[k]) * double(qv);
+      }
+    }
+    if (c >= 0) export_col<NL, T>(a.pf_out, c, x, i, j);
+    __syncthreads();
+    u = un;
+    c = cn;
+  }
+  const double tot = block_sum(pq, red);
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = tot;
+    zero_tail(a.part, U);
+  }
+}
+
+// r = b - A p in FP64 (p may be nullptr = 0; b may be nullptr -> r = A p), stored as TO * rscale.
+template <typename TO, int NL, int NQ>
+__global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
+  using C = Col<NL>;
+  __shared__ double tile[C::CPB * C::TS];
+  __shared__ double red[8];
+  const int t = threadIdx.x;
+  const LaneC<NL> L(t);
+  const int i = L.i, j = L.j;
+  const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
+  double np[NL], nb[NL], rf[6][NQ];
+  int kinds[6];
+  auto fetch = [&](int cc) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
+      np[k] = a.p ? a.p[g] : 0.0;
+      nb[k] = a.b ? a.b[g] : 0.0;
+    }
+    Slots<NQ> S;
+    slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      kinds[f] = S.kind[f];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) rf[f][q] = a.p ? a.pf[S.fine[f][q]] : 0.0;
+    }
+  };
+  int u = blockIdx.x;
+  int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
+  if (u < U) fetch(c < 0 ? 0 : c);
+  double rr = 0.0, bb = 0.0;
+  while (u < U) {
+    const int ce = c < 0 ? 0 : c;
+    double x[NL], bv[NL], hv[6];
+    double zlo, zhi;
+    const CubeMeta& m = a.g.meta[ce];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      x[k] = np[k];
+      bv[k] = nb[k];
+      tile[C::tix(L.s, i, j, k)] = x[k];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) hv[f] = halo_val<double, NQ>(kinds[f], rf[f]);
+    stage<NL, double>(tile, hv, L, zlo, zhi);
+    const double h = m.h * a.g.hscale;
+    const double ih2 = 1.0 / (h * h);
+    double d0, dm, dl;
+    diag<NL, double>(m, i, j, d0, dm, dl);
+    const double vol = m.vol;
+    const int un = u + G;
+    const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
+    __syncthreads();
+    if (un < U) fetch(cn < 0 ? 0 : cn);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const double d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
+      const double sum = nbsum<NL, double>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
+      const double ap = (sum - d * x[k]) * ih2;
+      const double r = a.b ? bv[k] - ap : ap;
+      if (c >= 0) {
+        if (a.b) bb += vol * bv[k] * bv[k];
+        rr += vol * r * r;
+        a.r[(size_t)c * C::N3 + k * C::N2 + L.l] = TO(r * a.rscale);
+      }
+    }
+    __syncthreads();
+    u = un;
+    c = cn;
+  }
+  if (a.part_rr) {
+    const double t0 = block_sum(rr, red);
+    __syncthreads();
+    const double t1 = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+      a.part_rr[blockIdx.x] = t0;
+      zero_tail(a.part_rr, U);
+      if (a.part_bb) {
+        a.part_bb[blockIdx.x] = t1;
+        zero_tail(a.part_bb, U);
+      }
+    }
+  }
+}
+
+// p += dscale d (when d is given) in FP64; export the faces of p.
+template <typename T, int NL>
+__global__ __launch_bounds__(256) void kc_ir(IrArgs<T> a) {
+  using C = Col<NL>;
+  const LaneC<NL> L(threadIdx.x);
+  const int U = col_units(C::CPB, a.g.n_cubes);
+  for (int u = blockIdx.x; u < U; u += gridDim.x) {
+    const int c = unit_cube<NL>(a.g, u, L.s);
+    if (c < 0) continue;
+    double p[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) p[k] = a.p[(size_t)c * C::N3 + k * C::N2 + L.l];
+    if (a.d) {
+      T d[NL];
+#pragma unroll
+      for (int k = 0; k < NL; ++k) d[k] = a.d[(size_t)c * C::N3 + k * C::N2 + L.l];
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        p[k] += a.dscale * double(d[k]);
+        a.p[(size_t)c * C::N3 + k * C::N2 + L.l] = p[k];
+      }
+    }
+    export_col<NL, double>(a.pf_out, c, p, L.i, L.j);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Projection step on 16^3 cubes (kernels_proj.hip has the versions for every cube size).
+// ------------------------------------------------------------------------------------------
+constexpr int P16 = Col<16>::P;
+__device__ __forceinline__ int tix16(int i, int j, int k) { return Col<16>::tix(0, i, j, k); }
+__device__ __forceinline__ int halo16(int f, int t) { return Col<16>::halo(0, f, t & 15, t >> 4); }
+
+template <typename T>
+__device__ __forceinline__ T face_get(const T* f, int c, int of, int t1, int t2) {
+  return f[(size_t)c * 1536 + of * 256 + t2 * 16 + t1];
+}
+
+// u* = (1 - alpha) u~ + alpha u_s, and the face-normal component of u* on each face.
+template <typename TF>
+__global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
+  const int t = threadIdx.x, i = t & 15, j = t >> 4;
+  const int n = a.g.n_cubes;
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int c = a.g.launch[w];
+    TF al[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) al[k] = a.alpha ? a.alpha[(size_t)c * 4096 + k * 256 + t] : TF(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      TF v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const size_t g = (size_t)c * 4096 + k * 256 + t;
+        const TF ut = a.u[d][g];
+        const TF us = a.us[d] ? a.us[d][g] : TF(a.usc[d]);
+        v[k] = a.alpha ? (TF(1) - al[k]) * ut + al[k] * us : ut;
+        a.ustar[d][g] = v[k];
+      }
+      TF* base = a.uf + (size_t)c * 1536;
+      if (d == 0) {
+        if (i == 0)
+#pragma unroll
+          for (int k = 0; k < 16; ++k) base[0 * 256 + k * 16 + j] = v[k];
+        if (i == 15)
+#pragma unroll
+          for (int k = 0; k < 16; ++k) base[1 * 256 + k * 16 + j] = v[k];
+      } else if (d == 1) {
+        if (j == 0)
+#pragma unroll
+          for (int k = 0; k < 16; ++k) base[2 * 256 + k * 16 + i] = v[k];
+        if (j == 15)
+#pragma unroll
+          for (int k = 0; k < 16; ++k) base[3 * 256 + k * 16 + i] = v[k];
+      } else {
+        base[4 * 256 + j * 16 + i] = v[0];
+        base[5 * 256 + j * 16 + i] = v[15];
+      }
+    }
+  }
+}
+
+// b = (rho/dt) div U*, U* = face-normal velocity (RULE_U interpolation at the cube faces).
+template <typename TF>
+__global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
+  __shared__ TF tile[16 * P16];
+  const int t = threadIdx.x, i = t & 15, j = t >> 4;
+  const int n = a.g.n_cubes;
+  const int t1 = t & 15, t2 = t >> 4;
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int c = a.g.launch[w];
+    const CubeMeta& m = a.g.meta[c];
+    const double ih = 1.0 / m.h;
+    double acc[16];
+    const auto gf = [&](int cc, int of, int aa, int bb) { return face_get(a.uf, cc, of, aa, bb); };
+    // z component: neighbours along k are this lane's registers
+    {
+      TF v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = a.ustar[2][(size_t)c * 4096 + k * 256 + t];
+      double lo, hi;  // face velocities on the -z and +z faces of the column
+      {
+        const int k4 = m.kind[4], k5 = m.kind[5];
+        const double r4 = k4 <= FK_FINER ? RuleTab<RULE_U>::nbeff(k4) * double(nb_raw<16, TF>(m, 4, t1, t2, gf)) : 0.0;
+        const double r5 = k5 <= FK_FINER ? RuleTab<RULE_U>::nbeff(k5) * double(nb_raw<16, TF>(m, 5, t1, t2, gf)) : 0.0;
+        lo = 0.5 * (k4 == FK_INFLOW ? 2.0 * a.U_in : r4) + RuleTab<RULE_U>::own(k4) * double(v[0]);
+        hi = 0.5 * (k5 == FK_INFLOW ? -2.0 * a.U_in : r5) + RuleTab<RULE_U>::own(k5) * double(v[15]);
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const double up = k < 15 ? 0.5 * (double(v[k]) + double(v[k < 15 ? k + 1 : 15])) : hi;
+        const double um = k > 0 ? 0.5 * (double(v[k > 0 ? k - 1 : 0]) + double(v[k])) : lo;
+        acc[k] = up - um;
+      }
+    }
+    // x and y components through the LDS plane tile
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      TF v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        v[k] = a.ustar[d][(size_t)c * 4096 + k * 256 + t];
+        tile[tix16(i, j, k)] = v[k];
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * d + s;
+        const int kd = m.kind[f];
+        TF hv = TF(0);
+        if (kd <= FK_FINER) hv = TF(RuleTab<RULE_U>::nbeff(kd)) * nb_raw<16, TF>(m, f, t1, t2, gf);
+        else if (kd == FK_INFLOW) hv = TF(2.0 * (s ? -a.U_in : a.U_in));
+        tile[halo16(f, t)] = hv;
+      }
+      __syncthreads();
+      const int st = d == 0 ? 1 : 18;
+      const double own_m = (d == 0 ? i == 0 : j == 0) ? RuleTab<RULE_U>::own(m.kind[2 * d]) : 0.5;
+      const double own_p = (d == 0 ? i == 15 : j == 15) ? RuleTab<RULE_U>::own(m.kind[2 * d + 1]) : 0.5;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int cc = tix16(i, j, k);
+        const double up = 0.5 * double(tile[cc + st]) + own_p * double(v[k]);
+        const double um = 0.5 * double(tile[cc - st]) + own_m * double(v[k]);
+        acc[k] += up - um;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a.b[(size_t)c * 4096 + k * 256 + t] = acc[k] * ih * a.inv_c;
+  }
+}
+
+// u_new = u* - c G_c p (cell velocities only; the face-velocity output uses k_correct).
+template <typename TF, int NQ>
+__global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
+  __shared__ double tile[16 * P16];
+  const int t = threadIdx.x, i = t & 15, j = t >> 4;
+  const int n = a.g.n_cubes;
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int c = a.g.launch[w];
+    const CubeMeta& m = a.g.meta[c];
+    double p[16], hv[6], rf[6][NQ];
+    double zlo, zhi;
+    Slots<NQ> S;
+    slots<16, NQ>(m, c, t & 15, t >> 4, S, false);
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) rf[f][q] = a.pf[S.fine[f][q]];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      p[k] = a.p[(size_t)c * 4096 + k * 256 + t];
+      tile[tix16(i, j, k)] = p[k];
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) hv[f] = halo_val<double, NQ>(S.kind[f], rf[f]);
+    stage<16, double>(tile, hv, LaneC<16>(t), zlo, zhi);
+    __syncthreads();
+    const double ch = a.c * 0.5 / m.h;
+    const double ox_m = i == 0 ? RuleTab<RULE_P>::own(m.kind[0]) : 1.0;
+    const double ox_p = i == 15 ? RuleTab<RULE_P>::own(m.kind[1]) : 1.0;
+    const double oy_m = j == 0 ? RuleTab<RULE_P>::own(m.kind[2]) : 1.0;
+    const double oy_p = j == 15 ? RuleTab<RULE_P>::own(m.kind[3]) : 1.0;
+    const double oz_m = RuleTab<RULE_P>::own(m.kind[4]), oz_p = RuleTab<RULE_P>::own(m.kind[5]);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int cc = tix16(i, j, k);
+      const size_t g = (size_t)c * 4096 + k * 256 + t;
+      const double gx = (tile[cc + 1] - ox_p * p[k]) - (tile[cc - 1] - ox_m * p[k]);
+      const double gy = (tile[cc + 18] - oy_p * p[k]) - (tile[cc - 18] - oy_m * p[k]);
+      const double zp = k < 15 ? p[k < 15 ? k + 1 : 15] - p[k] : zhi - oz_p * p[k];
+      const double zm = k > 0 ? p[k > 0 ? k - 1 : 0] - p[k] : zlo - oz_m * p[k];
+      if (a.unew[0]) a.unew[0][g] = TF(double(a.ustar[0][g]) - ch * gx);
+      if (a.unew[1]) a.unew[1][g] = TF(double(a.ustar[1][g]) - ch * gy);
+      if (a.unew[2]) a.unew[2][g] = TF(double(a.ustar[2][g]) - ch * (zp - zm));
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// Persistent grid of one kernel: every workgroup resident at once (CUs x occupancy), rounded
+// down to a multiple of 8 so each workgroup keeps to one XCD's stretch of the launch table.
+static int grid_for(const void* fn, int units) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1) per = 1;
+  int g = cus * per;
+  if (g >= 8) g -= g % 8;
+  return std::max(1, std::min(g, fine_grid(units)));
+}
+
+template <class K, class A>
+static hipError_t launch_col(K kernel, int cpb, const A& a, hipStream_t s) {
+  const int units = col_units(cpb, a.g.n_cubes);
+  hipLaunchKernelGGL(kernel, dim3(grid_for(reinterpret_cast<const void*>(kernel), units)), dim3(256),
+                     0, s, a);
+  return hipGetLastError();
+}
+
+#define BCM_COL_NL(NL, CALL)                            \
+  switch (NL) {                                         \
+    case 16: { constexpr int NLC = 16; CALL; } break;   \
+    case 8: { constexpr int NLC = 8; CALL; } break;     \
+    case 4: { constexpr int NLC = 4; CALL; } break;     \
+    case 2: { constexpr int NLC = 2; CALL; } break;     \
+    default: return hipErrorInvalidValue;               \
+  }
+
+template <typename T>
+hipError_t launchc_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s) {
+  BCM_COL_NL(NL, {
+    constexpr int cpb = Col<NLC>::CPB;
+    if (a.zero_init) return launch_col(kc_smooth<T, NLC, false, 1>, cpb, a, s);
+    if (a.g.multilevel) return launch_col(kc_smooth<T, NLC, true, 4>, cpb, a, s);
+    return launch_col(kc_smooth<T, NLC, true, 1>, cpb, a, s);
+  });
+  return hipSuccess;
+}
+template <typename T>
+hipError_t launchc_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s) {
+  BCM_COL_NL(NL, {
+    constexpr int cpb = Col<NLC>::CPB;
+    if (a.g.multilevel) return launch_col(kc_restrict<T, NLC, 4>, cpb, a, s);
+    return launch_col(kc_restrict<T, NLC, 1>, cpb, a, s);
+  });
+  return hipSuccess;
+}
+template <typename T>
+hipError_t launchc_apply(int NL, const ApplyArgs<T>& a, hipStream_t s) {
+  BCM_COL_NL(NL, {
+    constexpr int cpb = Col<NLC>::CPB;
+    if (a.g.multilevel) return launch_col(kc_apply<T, NLC, 4>, cpb, a, s);
+    return launch_col(kc_apply<T, NLC, 1>, cpb, a, s);
+  });
+  return hipSuccess;
+}
+template <typename TO>
+hipError_t launchc_resid64(int NL, const Resid64Args<TO>& a, hipStream_t s) {
+  BCM_COL_NL(NL, {
+    constexpr int cpb = Col<NLC>::CPB;
+    if (a.g.multilevel) return launch_col(kc_resid64<TO, NLC, 4>, cpb, a, s);
+    return launch_col(kc_resid64<TO, NLC, 1>, cpb, a, s);
+  });
+  return hipSuccess;
+}
+template <typename T>
+hipError_t launchc_ir(int NL, const IrArgs<T>& a, hipStream_t s) {
+  BCM_COL_NL(NL, {
+    const int units = col_units(Col<NLC>::CPB, a.g.n_cubes);
+    hipLaunchKernelGGL((kc_ir<T, NLC>), dim3(std::min(units, 4096)), dim3(256), 0, s, a);
+    return hipGetLastError();
+  });
+  return hipSuccess;
+}
+template <typename TF>
+hipError_t launch16_force(const ForceArgs<TF>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k16_force<TF>), dim3(std::min(a.g.n_cubes, 2048)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename TF>
+hipError_t launch16_div(const DivArgs<TF>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k16_div<TF>), dim3(std::min(a.g.n_cubes, 2048)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename TF>
+hipError_t launch16_correct(const CorrectArgs<TF>& a, hipStream_t s) {
+  if (a.g.multilevel)
+    hipLaunchKernelGGL((k16_correct<TF, 4>), dim3(std::min(a.g.n_cubes, 2048)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k16_correct<TF, 1>), dim3(std::min(a.g.n_cubes, 2048)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+#define BCM_INSTC(T)                                                                  \
+  template hipError_t launchc_smooth<T>(int, const SmoothArgs<T>&, hipStream_t);      \
+  template hipError_t launchc_restrict<T>(int, const RestrictArgs<T>&, hipStream_t);  \
+  template hipError_t launchc_apply<T>(int, const ApplyArgs<T>&, hipStream_t);        \
+  template hipError_t launchc_resid64<T>(int, const Resid64Args<T>&, hipStream_t);    \
+  template hipError_t launchc_ir<T>(int, const IrArgs<T>&, hipStream_t);              \
+  template hipError_t launch16_force<T>(const ForceArgs<T>&, hipStream_t);            \
+  template hipError_t launch16_div<T>(const DivArgs<T>&, hipStream_t);                \
+  template hipError_t launch16_correct<T>(const CorrectArgs<T>&, hipStream_t);
+BCM_INSTC(float)
+BCM_INSTC(double)
+
+}  // namespace bcm

@@ -1,194 +1,17 @@
-// Multigrid and Krylov kernels of the pressure Poisson solve (Sec. 3): red-black Gauss-Seidel
-// smoothing, residual + restriction, operator apply fused with the search-direction update,
-// vector updates with fused norms, FP64 residual for iterative refinement, and the
-// conjugate-gradient solve on the one-cell-per-cube level (Sec. 7: at most 10 iterations).
+// Krylov, reduction and coarse-level kernels of the pressure Poisson solve (Sec. 3): the
+// vector update with its fused norm, face export, the deterministic reduction of partial
+// sums, the conjugate-gradient solve on the one-cell-per-cube level (Sec. 7: at most 10
+// iterations) and multigrid on the cube graph that replaces it by default.  The stencil
+// kernels of the per-cube levels are in kernels_col.hip.
 //
-// One workgroup (256 lanes = 4 wave64) owns one 16^3 or 8^3 cube, or several smaller cubes,
-// staged as an LDS tile with a one-cell halo (tile.hpp).  All sums are accumulated in FP64
-// with a fixed reduction order: each workgroup writes one partial, k_finalize sums them.
+// All sums are accumulated in FP64 with a fixed reduction order: each workgroup writes one
+// partial, k_finalize sums them.
 #include "kernels.hpp"
 #include "tile.hpp"
 
 namespace bcm {
 
 namespace {
-
-// ------------------------------------------------------------------------------------------
-// Red-black Gauss-Seidel smoothing inside each cube (halo frozen at launch: the sweep is
-// Gauss-Seidel within a cube and Jacobi across cube faces).  Optionally starts from zero,
-// optionally adds a piecewise-constant prolongation of a coarse correction first, and
-// optionally accumulates <x, r_dot>_V and <x, q_dot>_V for the Krylov wrapper.
-// ------------------------------------------------------------------------------------------
-template <int NL, typename T>
-__global__ __launch_bounds__(256) void k_smooth(SmoothArgs<T> a) {
-  using L = Lv<NL>;
-  constexpr int R = (L::CPB * L::N3 + WG - 1) / WG;
-  __shared__ CubeMeta sm[L::CPB];
-  __shared__ int cube[L::CPB];
-  __shared__ T tile[L::CPB * L::TILE];
-  __shared__ double red[8];
-  load_meta<NL>(sm, cube, a.g.meta, a.g.launch, a.g.n_cubes);
-  T bv[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int e = threadIdx.x + r * WG;
-    bv[r] = T(0);
-    if (e >= L::CPB * L::N3) continue;
-    int s, i, j, k;
-    cell_of<NL>(e, s, i, j, k);
-    const int c = cube[s];
-    if (c < 0) continue;
-    const size_t g = (size_t)c * L::N3 + (e - s * L::N3);
-    T v = a.zero_init ? T(0) : a.x[g];
-    if (a.xc) {
-      constexpr int NC = NL / 2;
-      v += a.xc[(size_t)c * (NC * NC * NC) + ((k >> 1) * NC + (j >> 1)) * NC + (i >> 1)];
-    }
-    tile[s * L::TILE + ti<NL>(i, j, k)] = v;
-    bv[r] = a.b[g];
-  }
-  if (a.xc)
-    fill_halo<NL, RULE_P, T>(tile, sm, cube,
-                             FaceGetProlong<NL, T>{a.zero_init ? nullptr : a.xf_in, a.xcf},
-                             BcZero<T>{});
-  else if (a.zero_init)
-    zero_halo<NL, T>(tile, cube);
-  else
-    fill_halo<NL, RULE_P, T>(tile, sm, cube, FaceGet<NL, T>{a.xf_in}, BcZero<T>{});
-  __syncthreads();
-  for (int sw = 0; sw < a.sweeps; ++sw) {
-    for (int col = 0; col < 2; ++col) {
-      const int colour = col ^ a.black_first;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int e = threadIdx.x + r * WG;
-        if (e >= L::CPB * L::N3) continue;
-        int s, i, j, k;
-        cell_of<NL>(e, s, i, j, k);
-        if (((i + j + k) & 1) != colour || cube[s] < 0) continue;
-        const CubeMeta& m = sm[s];
-        const T h = T(m.h * a.g.hscale);
-        T nb, dg;
-        stencil_p<NL, T>(tile + s * L::TILE, m, i, j, k, nb, dg);
-        tile[s * L::TILE + ti<NL>(i, j, k)] = (nb - h * h * bv[r]) / dg;
-      }
-      __syncthreads();
-    }
-  }
-  double zr = 0.0, zq = 0.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int e = threadIdx.x + r * WG;
-    if (e >= L::CPB * L::N3) continue;
-    int s, i, j, k;
-    cell_of<NL>(e, s, i, j, k);
-    const int c = cube[s];
-    if (c < 0) continue;
-    const size_t g = (size_t)c * L::N3 + (e - s * L::N3);
-    const T v = tile[s * L::TILE + ti<NL>(i, j, k)];
-    a.x[g] = v;
-    if (a.part_zr) {
-      const double w = sm[s].vol;
-      zr += w * double(v) * double(a.r_dot[g]);
-      if (a.q_dot) zq += w * double(v) * double(a.q_dot[g]);
-    }
-  }
-  export_faces<NL, T, T>(a.xf_out, tile, cube);
-  if (a.part_zr) {
-    const double t0 = block_sum(zr, red);
-    __syncthreads();
-    const double t1 = block_sum(zq, red);
-    if (threadIdx.x == 0) {
-      a.part_zr[blockIdx.x] = t0;
-      if (a.part_zq) a.part_zq[blockIdx.x] = t1;
-    }
-  }
-}
-
-// Residual r = b - A x, restricted to the next level by the mean of the 8 children.
-template <int NL, typename T>
-__global__ __launch_bounds__(256) void k_restrict(RestrictArgs<T> a) {
-  using L = Lv<NL>;
-  constexpr int NC = NL / 2, NC3 = NC * NC * NC;
-  __shared__ CubeMeta sm[L::CPB];
-  __shared__ int cube[L::CPB];
-  __shared__ T tile[L::CPB * L::TILE];
-  load_meta<NL>(sm, cube, a.g.meta, a.g.launch, a.g.n_cubes);
-  for (int e = threadIdx.x; e < L::CPB * L::N3; e += WG) {
-    int s, i, j, k;
-    cell_of<NL>(e, s, i, j, k);
-    const int c = cube[s];
-    if (c < 0) continue;
-    tile[s * L::TILE + ti<NL>(i, j, k)] = a.x[(size_t)c * L::N3 + (e - s * L::N3)];
-  }
-  fill_halo<NL, RULE_P, T>(tile, sm, cube, FaceGet<NL, T>{a.xf}, BcZero<T>{});
-  __syncthreads();
-  for (int e = threadIdx.x; e < L::CPB * NC3; e += WG) {
-    const int s = e / NC3;
-    const int cc = e - s * NC3;
-    const int c = cube[s];
-    if (c < 0) continue;
-    const int I = cc % NC, J = (cc / NC) % NC, K = cc / (NC * NC);
-    const CubeMeta& m = sm[s];
-    const T h = T(m.h * a.g.hscale);
-    const T ih2 = T(1) / (h * h);
-    T acc = T(0);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
-      T nb, dg;
-      stencil_p<NL, T>(tile + s * L::TILE, m, i, j, k, nb, dg);
-      const T x = tile[s * L::TILE + ti<NL>(i, j, k)];
-      acc += a.b[(size_t)c * L::N3 + (k * NL + j) * NL + i] - (nb - dg * x) * ih2;
-    }
-    a.bc[(size_t)c * NC3 + cc] = acc * T(0.125);
-  }
-}
-
-// p = z + beta p (or p = z); q = A p; partial <p, q>_V.
-template <int NL, typename T>
-__global__ __launch_bounds__(256) void k_apply(ApplyArgs<T> a) {
-  using L = Lv<NL>;
-  __shared__ CubeMeta sm[L::CPB];
-  __shared__ int cube[L::CPB];
-  __shared__ T tile[L::CPB * L::TILE];
-  __shared__ double red[8];
-  load_meta<NL>(sm, cube, a.g.meta, a.g.launch, a.g.n_cubes);
-  const T beta = a.first ? T(0) : T(a.sc->beta);
-  for (int e = threadIdx.x; e < L::CPB * L::N3; e += WG) {
-    int s, i, j, k;
-    cell_of<NL>(e, s, i, j, k);
-    const int c = cube[s];
-    if (c < 0) continue;
-    const size_t g = (size_t)c * L::N3 + (e - s * L::N3);
-    tile[s * L::TILE + ti<NL>(i, j, k)] = a.first ? a.z[g] : a.z[g] + beta * a.p[g];
-  }
-  if (a.first)
-    fill_halo<NL, RULE_P, T>(tile, sm, cube, FaceGet<NL, T>{a.zf}, BcZero<T>{});
-  else
-    fill_halo<NL, RULE_P, T>(tile, sm, cube, FaceGetAxpy<NL, T>{a.zf, a.pf_in, beta}, BcZero<T>{});
-  __syncthreads();
-  double pq = 0.0;
-  for (int e = threadIdx.x; e < L::CPB * L::N3; e += WG) {
-    int s, i, j, k;
-    cell_of<NL>(e, s, i, j, k);
-    const int c = cube[s];
-    if (c < 0) continue;
-    const CubeMeta& m = sm[s];
-    const size_t g = (size_t)c * L::N3 + (e - s * L::N3);
-    const T h = T(m.h * a.g.hscale);
-    T nb, dg;
-    stencil_p<NL, T>(tile + s * L::TILE, m, i, j, k, nb, dg);
-    const T pv = tile[s * L::TILE + ti<NL>(i, j, k)];
-    const T qv = (nb - dg * pv) / (h * h);
-    a.p[g] = pv;
-    a.q[g] = qv;
-    pq += m.vol * double(pv) * double(qv);
-  }
-  export_faces<NL, T, T>(a.pf_out, tile, cube);
-  const double t = block_sum(pq, red);
-  if (threadIdx.x == 0) a.part[blockIdx.x] = t;
-}
 
 // x += alpha p; r -= alpha q; partial <r, r>_V.  One workgroup per cube.
 template <typename T>
@@ -207,84 +30,6 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   }
   const double t = block_sum(rr, red);
   if (threadIdx.x == 0) a.part[c] = t * a.meta[c].vol;
-}
-
-// r = b - A p (FP64), stored as TO scaled by rscale; partial <r,r>_V and <b,b>_V.
-// With b == nullptr it computes r = A p instead (operator apply).
-template <int NL, typename TO>
-__global__ __launch_bounds__(256) void k_resid64(Resid64Args<TO> a) {
-  using L = Lv<NL>;
-  __shared__ CubeMeta sm[L::CPB];
-  __shared__ int cube[L::CPB];
-  __shared__ double tile[L::CPB * L::TILE];
-  __shared__ double red[8];
-  load_meta<NL>(sm, cube, a.g.meta, a.g.launch, a.g.n_cubes);
-  for (int e = threadIdx.x; e < L::CPB * L::N3; e += WG) {
-    int s, i, j, k;
-    cell_of<NL>(e, s, i, j, k);
-    const int c = cube[s];
-    if (c < 0) continue;
-    tile[s * L::TILE + ti<NL>(i, j, k)] = a.p ? a.p[(size_t)c * L::N3 + (e - s * L::N3)] : 0.0;
-  }
-  if (a.p)
-    fill_halo<NL, RULE_P, double>(tile, sm, cube, FaceGet<NL, double>{a.pf}, BcZero<double>{});
-  else
-    zero_halo<NL, double>(tile, cube);
-  __syncthreads();
-  double rr = 0.0, bb = 0.0;
-  for (int e = threadIdx.x; e < L::CPB * L::N3; e += WG) {
-    int s, i, j, k;
-    cell_of<NL>(e, s, i, j, k);
-    const int c = cube[s];
-    if (c < 0) continue;
-    const CubeMeta& m = sm[s];
-    const size_t g = (size_t)c * L::N3 + (e - s * L::N3);
-    const double h = m.h * a.g.hscale;
-    double nb, dg;
-    stencil_p<NL, double>(tile + s * L::TILE, m, i, j, k, nb, dg);
-    const double ap = (nb - dg * tile[s * L::TILE + ti<NL>(i, j, k)]) / (h * h);
-    double r;
-    if (a.b) {
-      const double bv = a.b[g];
-      r = bv - ap;
-      bb += m.vol * bv * bv;
-    } else {
-      r = ap;
-    }
-    rr += m.vol * r * r;
-    a.r[g] = TO(r * a.rscale);
-  }
-  if (a.part_rr) {
-    const double t0 = block_sum(rr, red);
-    __syncthreads();
-    const double t1 = block_sum(bb, red);
-    if (threadIdx.x == 0) {
-      a.part_rr[blockIdx.x] = t0;
-      if (a.part_bb) a.part_bb[blockIdx.x] = t1;
-    }
-  }
-}
-
-// p += d (refinement update) and export the faces of p.
-template <int NL, typename T>
-__global__ __launch_bounds__(256) void k_ir(IrArgs<T> a) {
-  using L = Lv<NL>;
-  __shared__ CubeMeta sm[L::CPB];
-  __shared__ int cube[L::CPB];
-  __shared__ double tile[L::CPB * L::TILE];
-  load_meta<NL>(sm, cube, a.g.meta, a.g.launch, a.g.n_cubes);
-  for (int e = threadIdx.x; e < L::CPB * L::N3; e += WG) {
-    int s, i, j, k;
-    cell_of<NL>(e, s, i, j, k);
-    const int c = cube[s];
-    if (c < 0) continue;
-    const size_t g = (size_t)c * L::N3 + (e - s * L::N3);
-    const double v = (a.d ? a.p[g] + a.dscale * double(a.d[g]) : a.p[g]);
-    if (a.d) a.p[g] = v;
-    tile[s * L::TILE + ti<NL>(i, j, k)] = v;
-  }
-  __syncthreads();
-  export_faces<NL, double, double>(a.pf_out, tile, cube);
 }
 
 // Face export of a field (or of the face-normal components of a vector field).
@@ -565,6 +310,50 @@ __device__ void g_bottom(const GLevel<T>& L, int iters, double* w, double* red) 
   __syncthreads();
 }
 
+// b = volume-weighted restriction of the finer level's residual r; x = 0.  With at most 8
+// children (every merge here is 2x2x2 or a subset) all loads of a node are issued before use.
+template <typename T>
+__device__ void g_restrict(const GLevel<T>& C, const T* r) {
+  for (int J = threadIdx.x; J < C.n; J += blockDim.x) {
+    T acc = T(0);
+    if (C.CW <= 8) {
+      int ch[8];
+      T wt[8], rv[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        ch[w] = w < C.CW ? C.child[size_t(w) * C.n + J] : -1;
+        wt[w] = w < C.CW ? C.child_w[size_t(w) * C.n + J] : T(0);
+      }
+#pragma unroll
+      for (int w = 0; w < 8; ++w) rv[w] = r[ch[w] >= 0 ? ch[w] : 0];
+#pragma unroll
+      for (int w = 0; w < 8; ++w)
+        if (ch[w] >= 0) acc += wt[w] * rv[w];
+    } else {
+      for (int w = 0; w < C.CW; ++w) {
+        const size_t o = size_t(w) * C.n + J;
+        const int ch = C.child[o];
+        if (ch >= 0) acc += C.child_w[o] * r[ch];
+      }
+    }
+    C.b[J] = acc;
+    C.x[J] = T(0);
+  }
+  __syncthreads();
+}
+
+// Direct solve of the (small) last level with its inverse precomputed on the host.
+template <typename T>
+__device__ void g_direct(const GLevel<T>& L, const T* inv_t) {
+  const int n = L.n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    T acc = T(0);
+    for (int j = 0; j < n; ++j) acc += inv_t[j * n + i] * L.b[j];
+    L.x[i] = acc;
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
   extern __shared__ __align__(16) unsigned char gsm[];
@@ -589,21 +378,12 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
     for (int g = 0; g + 1 < G; ++g) {
       g_smooth(lv[g], a.pre, true);
       g_residual(lv[g]);
-      const GLevel<T>& C = lv[g + 1];
-      const T* r = lv[g].r;
-      for (int J = threadIdx.x; J < C.n; J += blockDim.x) {
-        T acc = T(0);
-        for (int w = 0; w < C.CW; ++w) {
-          const size_t o = size_t(w) * C.n + J;
-          const int ch = C.child[o];
-          if (ch >= 0) acc += C.child_w[o] * r[ch];
-        }
-        C.b[J] = acc;
-        C.x[J] = T(0);
-      }
-      __syncthreads();
+      g_restrict(lv[g + 1], lv[g].r);
     }
-    g_bottom(lv[G - 1], a.bottom_iters, a.w, red);
+    if (a.binv)
+      g_direct(lv[G - 1], a.binv);
+    else
+      g_bottom(lv[G - 1], a.bottom_iters, a.w, red);
     for (int g = G - 2; g >= 0; --g) {
       const GLevel<T>& F = lv[g];
       const T* xc = lv[g + 1].x;
@@ -648,21 +428,15 @@ static inline int n_wg(int NL, int n_cubes) {
 
 template <typename T>
 hipError_t launch_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s) {
-  if (NL == 16) return launch16_smooth<T>(a, s);
-  BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_smooth<NLC, T>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
-  return hipGetLastError();
+  return launchc_smooth<T>(NL, a, s);
 }
 template <typename T>
 hipError_t launch_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s) {
-  if (NL == 16) return launch16_restrict<T>(a, s);
-  BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_restrict<NLC, T>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
-  return hipGetLastError();
+  return launchc_restrict<T>(NL, a, s);
 }
 template <typename T>
 hipError_t launch_apply(int NL, const ApplyArgs<T>& a, hipStream_t s) {
-  if (NL == 16) return launch16_apply<T>(a, s);
-  BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_apply<NLC, T>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
-  return hipGetLastError();
+  return launchc_apply<T>(NL, a, s);
 }
 template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, hipStream_t s) {
@@ -671,14 +445,11 @@ hipError_t launch_update(const UpdateArgs<T>& a, hipStream_t s) {
 }
 template <typename TO>
 hipError_t launch_resid64(int NL, const Resid64Args<TO>& a, hipStream_t s) {
-  if (NL == 16) return launch16_resid64<TO>(a, s);
-  BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_resid64<NLC, TO>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
-  return hipGetLastError();
+  return launchc_resid64<TO>(NL, a, s);
 }
 template <typename T>
 hipError_t launch_ir(int NL, const IrArgs<T>& a, hipStream_t s) {
-  BCM_DISPATCH_NL(NL, hipLaunchKernelGGL((k_ir<NLC, T>), dim3(n_wg(NLC, a.g.n_cubes)), dim3(WG), 0, s, a));
-  return hipGetLastError();
+  return launchc_ir<T>(NL, a, s);
 }
 template <typename T, typename TO>
 hipError_t launch_export(int NL, const ExportArgs<T, TO>& a, hipStream_t s) {

@@ -86,7 +86,7 @@ struct bcm_plan {
     int lds_x, lds_b, lds_r;
   };
   std::vector<GOff> g_off;
-  size_t o_glev = 0, o_gw = 0, o_perm0 = 0;
+  size_t o_glev = 0, o_gw = 0, o_perm0 = 0, o_ginv = 0;
   int g_lds = 0;
   Timer timer;
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
@@ -205,7 +205,8 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
     CoarseMGArgs<T> ga{B(L - 1), X(L - 1), F(1, L - 1), P->at<const GLevel<T>>(P->o_glev),
                        P->at<const int32_t>(P->o_perm0), int(P->g_off.size()), o.coarse_cycles,
                        2, 2, std::max(o.coarse_iters, 64),  // the last graph level has <= 64 nodes
-                       P->at<double>(P->o_gw), P->g_lds};
+                       P->at<double>(P->o_gw),
+                       P->M->coarse.bottom_inv.empty() ? nullptr : P->at<const T>(P->o_ginv), P->g_lds};
     HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse_mg<T>(ga, s); }), "k_coarse_mg");
   } else {
     CoarseArgs<T> ca{P->at<const CubeMeta>(P->o_meta), P->nc, double(P->n), B(L - 1), X(L - 1),
@@ -530,7 +531,7 @@ int upload_graph(bcm_plan* P, hipStream_t s) {
     keep.emplace_back(v.begin(), v.end());
     return keep.back();
   };
-  keep.reserve(4 * Ls.size());
+  keep.reserve(4 * Ls.size() + 1);
   for (size_t g = 0; g < Ls.size(); ++g) {
     const CoarseLevel& L = Ls[g];
     const bcm_plan::GOff& o = P->g_off[g];
@@ -565,6 +566,8 @@ int upload_graph(bcm_plan* P, hipStream_t s) {
     d.r = P->at<T>(o.r);
   }
   HIPCHK(put(P->o_perm0, Ls[0].perm.data(), Ls[0].perm.size() * 4), "upload graph permutation");
+  HIPCHK(put(P->o_ginv, conv(P->M->coarse.bottom_inv).data(), P->M->coarse.bottom_inv.size() * sizeof(T)),
+         "upload bottom inverse");
   HIPCHK(put(P->o_glev, lev.data(), lev.size() * sizeof(GLevel<T>)), "upload graph levels");
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   return BCM_OK;
@@ -640,7 +643,8 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   size_t top = 0;
   P->o_meta = take(top, nc * sizeof(CubeMeta));
   P->o_launch = take(top, nc * sizeof(int32_t));
-  for (int i = 0; i < 3; ++i) P->o_part[i] = take(top, nc * sizeof(double));
+  const size_t nparts = std::max(nc, size_t(partials_of(P->n, int(nc))));
+  for (int i = 0; i < 3; ++i) P->o_part[i] = take(top, nparts * sizeof(double));
   P->o_sc = take(top, sizeof(Scalars));
   P->o_cw = take(top, 4 * nc * sizeof(double));
   for (int d = 0; d < 3; ++d) P->o_ustar[d] = take(top, cells * Tf);
@@ -708,6 +712,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
     P->o_glev = take(top, Ls.size() * sizeof(GLevel<double>));
     P->o_gw = take(top, 4 * size_t(Ls.back().n) * sizeof(double));
     P->o_perm0 = take(top, Ls[0].perm.size() * 4);
+    P->o_ginv = take(top, M.coarse.bottom_inv.size() * sizeof(double));
   }
   P->ws_bytes = top;
   if (workspace_bytes) *workspace_bytes = top;
