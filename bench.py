@@ -31,7 +31,7 @@ PEAK_HBM_GBS = 8000.0
 def alg_bytes_per_cell(cls, s, f):
     return {
         "presmooth16": 2 * s,            # read b, write x (zero initial guess)
-        "postsmooth16": 3 * s + s / 8,   # read x, b, coarse correction; write x
+        "postsmooth16": 4 * s + s / 8,   # read x, b, q, coarse correction; write x
         "restrict16": 2 * s + s / 8,     # read x, b; write restricted residual
         "apply16": 4 * s,                # read z, p; write p, q
         "update": 6 * s,                 # read x, p, r, q; write x, r
@@ -45,6 +45,52 @@ def alg_bytes_per_cell(cls, s, f):
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    """sha256 of the library sources: counter figures recorded for other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1808_04099_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_cls, workload_name, precision):
+    """HBM bytes per launch of a kernel class from the recorded rocprofv3 FETCH_SIZE and
+    WRITE_SIZE passes (scaled by the copy-kernel calibration), or None when no figure exists
+    for these sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_sha256") != source_hash():
+        return None
+    e = d.get("kernels", {}).get(f"{workload_name}/{precision}/{kernel_cls}")
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def copy_probe(nbytes=1 << 30, reps=10):
+    """Device-to-device copy of nbytes (read + write) with torch: the practical HBM ceiling,
+    and the known-size kernel that calibrates the byte counters."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def workload(name):
@@ -136,14 +182,18 @@ def run(args):
     for _ in range(args.warmup):
         rep = step(plan, u, a, out)
     torch.cuda.synchronize()
-    # find the dominant kernel class over one untimed step (one class timed per step)
+    # time each kernel class over one untimed step (one class timed per step); the dominant
+    # one is the class with the largest share of the step
     dominant, best = args.kernel, -1.0
-    if dominant is None:
-        for cls in ("presmooth16", "postsmooth16", "restrict16", "apply16", "update", "resid64"):
-            _, _, (nl, tot) = timed_steps(plan, u, a, out, 1, cls)
-            log(f"[bench] {cls}: {nl} launches, {tot:.3f} ms per step")
-            if tot > best:
-                dominant, best = cls, tot
+    class_ms = {}
+    for cls in () if args.kernel else ("presmooth16", "postsmooth16", "restrict16", "apply16",
+                                       "update", "resid64", "ir", "coarse", "force", "div",
+                                       "correct"):
+        _, _, (nl, tot) = timed_steps(plan, u, a, out, 1, cls)
+        class_ms[cls] = {"launches": nl, "ms_per_step": tot}
+        log(f"[bench] {cls}: {nl} launches, {tot:.3f} ms per step")
+        if args.kernel is None and cls != "coarse" and tot > best:
+            dominant, best = cls, tot
     ms, reps, (nl, tot) = timed_steps(plan, u, a, out, args.steps, dominant)
     rep = reps[-1]
     sweeps = plan.opts.pre_sweeps + plan.opts.post_sweeps
@@ -177,8 +227,10 @@ def run(args):
                        "cell_updates_per_step": updates},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": None, "alg_bytes_per_cell": bpc,
+                     "traffic": measured_traffic(dominant, args.workload, prec),
+                     "alg_bytes_per_launch": bpc * n_cells, "alg_bytes_per_cell": bpc,
                      "launches": nl, "avg_launch_ms": avg_ms},
+        "kernel_classes": class_ms,
     }
     if args.compare_fp64 and prec != "fp64":
         del plan, out
@@ -194,6 +246,11 @@ def run(args):
         log(f"[bench] fp64: {ms64:.2f} ms/step, {reps64[-1].n_inner} its; "
             f"mixed speed-up {ms64 / ms:.2f}x")
         del p64, o64
+    if args.copy_probe:
+        cp = copy_probe()
+        result["copy_probe"] = cp
+        log(f"[bench] torch device copy: {cp['gbs']:.0f} GB/s (read + write of "
+            f"{cp['bytes_per_copy'] // 2} bytes)")
     if args.cpu_baseline:
         log("[bench] timing the CPU oracle ...")
         cb = cpu_baseline(pr, args.cpu_seconds)
@@ -209,9 +266,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="mixed_channel")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed_f32fields"])
-    ap.add_argument("--kernel", default=None, help="timer class for the roofline")
+    ap.add_argument("--kernel", default=None,
+                    help="timer class for the roofline (skips the per-class survey)")
     ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--no-copy-probe", dest="copy_probe", action="store_false",
+                    help="skip the device-copy bandwidth probe")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--opt", action="append", default=[],
                     help="solver option override key=value (e.g. coarse_iters=40)")

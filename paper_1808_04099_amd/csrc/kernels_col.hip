@@ -599,45 +599,41 @@ __device__ __forceinline__ T face_get(const T* f, int c, int of, int t1, int t2)
   return f[(size_t)c * 1536 + of * 256 + t2 * 16 + t1];
 }
 
-// u* = (1 - alpha) u~ + alpha u_s, and the face-normal component of u* on each face.
+// u* = (1 - alpha) u~ + alpha u_s, and the face-normal component of u* on each face.  A pure
+// stream: planes are processed four at a time so that few values are live per lane.
 template <typename TF>
 __global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
   const int n = a.g.n_cubes;
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
     const int c = a.g.launch[w];
-    TF al[16];
+    TF* base = a.uf + (size_t)c * 1536;
+#pragma unroll 1
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+      TF v[3][4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) al[k] = a.alpha ? a.alpha[(size_t)c * 4096 + k * 256 + t] : TF(0);
+      for (int kk = 0; kk < 4; ++kk) {
+        const size_t g = (size_t)c * 4096 + (k0 + kk) * 256 + t;
+        const TF al = a.alpha ? a.alpha[g] : TF(0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      TF v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const size_t g = (size_t)c * 4096 + k * 256 + t;
-        const TF ut = a.u[d][g];
-        const TF us = a.us[d] ? a.us[d][g] : TF(a.usc[d]);
-        v[k] = a.alpha ? (TF(1) - al[k]) * ut + al[k] * us : ut;
-        a.ustar[d][g] = v[k];
+        for (int d = 0; d < 3; ++d) {
+          const TF ut = a.u[d][g];
+          const TF us = a.us[d] ? a.us[d][g] : TF(a.usc[d]);
+          v[d][kk] = a.alpha ? (TF(1) - al) * ut + al * us : ut;
+        }
       }
-      TF* base = a.uf + (size_t)c * 1536;
-      if (d == 0) {
-        if (i == 0)
 #pragma unroll
-          for (int k = 0; k < 16; ++k) base[0 * 256 + k * 16 + j] = v[k];
-        if (i == 15)
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = k0 + kk;
+        const size_t g = (size_t)c * 4096 + k * 256 + t;
 #pragma unroll
-          for (int k = 0; k < 16; ++k) base[1 * 256 + k * 16 + j] = v[k];
-      } else if (d == 1) {
-        if (j == 0)
-#pragma unroll
-          for (int k = 0; k < 16; ++k) base[2 * 256 + k * 16 + i] = v[k];
-        if (j == 15)
-#pragma unroll
-          for (int k = 0; k < 16; ++k) base[3 * 256 + k * 16 + i] = v[k];
-      } else {
-        base[4 * 256 + j * 16 + i] = v[0];
-        base[5 * 256 + j * 16 + i] = v[15];
+        for (int d = 0; d < 3; ++d) a.ustar[d][g] = v[d][kk];
+        if (i == 0) base[0 * 256 + k * 16 + j] = v[0][kk];
+        if (i == 15) base[1 * 256 + k * 16 + j] = v[0][kk];
+        if (j == 0) base[2 * 256 + k * 16 + i] = v[1][kk];
+        if (j == 15) base[3 * 256 + k * 16 + i] = v[1][kk];
+        if (k == 0) base[4 * 256 + j * 16 + i] = v[2][kk];
+        if (k == 15) base[5 * 256 + j * 16 + i] = v[2][kk];
       }
     }
   }
@@ -712,46 +708,52 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
   }
 }
 
-// u_new = u* - c G_c p (cell velocities only; the face-velocity output uses k_correct).
+// u_new = u* - c G_c p (cell velocities only; the face-velocity output uses k_correct).  The
+// x/y neighbours of p go through LDS one plane at a time (two plane buffers used in turn);
+// the halo ring of plane k comes from the lanes with j == k, which hold the x/y face values
+// at z = k (tangential position (t1, t2) = (i, j) of faces 0..3).
 template <typename TF, int NQ>
 __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
-  __shared__ double tile[16 * P16];
+  __shared__ double pl[2][P16];
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
   const int n = a.g.n_cubes;
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
     const int c = a.g.launch[w];
     const CubeMeta& m = a.g.meta[c];
     double p[16], hv[6], rf[6][NQ];
-    double zlo, zhi;
     Slots<NQ> S;
-    slots<16, NQ>(m, c, t & 15, t >> 4, S, false);
+    slots<16, NQ>(m, c, i, j, S, false);
 #pragma unroll
     for (int f = 0; f < 6; ++f)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) rf[f][q] = a.pf[S.fine[f][q]];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      p[k] = a.p[(size_t)c * 4096 + k * 256 + t];
-      tile[tix16(i, j, k)] = p[k];
-    }
+    for (int k = 0; k < 16; ++k) p[k] = a.p[(size_t)c * 4096 + k * 256 + t];
 #pragma unroll
     for (int f = 0; f < 6; ++f) hv[f] = halo_val<double, NQ>(S.kind[f], rf[f]);
-    stage<16, double>(tile, hv, LaneC<16>(t), zlo, zhi);
-    __syncthreads();
     const double ch = a.c * 0.5 / m.h;
     const double ox_m = i == 0 ? RuleTab<RULE_P>::own(m.kind[0]) : 1.0;
     const double ox_p = i == 15 ? RuleTab<RULE_P>::own(m.kind[1]) : 1.0;
     const double oy_m = j == 0 ? RuleTab<RULE_P>::own(m.kind[2]) : 1.0;
     const double oy_p = j == 15 ? RuleTab<RULE_P>::own(m.kind[3]) : 1.0;
     const double oz_m = RuleTab<RULE_P>::own(m.kind[4]), oz_p = RuleTab<RULE_P>::own(m.kind[5]);
+    const int cc = (j + 1) * 18 + (i + 1);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int cc = tix16(i, j, k);
+      double* b = pl[k & 1];
+      b[cc] = p[k];
+      if (j == k) {
+        b[(i + 1) * 18 + 0] = hv[0];   // x = -1, y = i
+        b[(i + 1) * 18 + 17] = hv[1];  // x = 16, y = i
+        b[0 * 18 + (i + 1)] = hv[2];   // y = -1, x = i
+        b[17 * 18 + (i + 1)] = hv[3];  // y = 16, x = i
+      }
+      __syncthreads();
       const size_t g = (size_t)c * 4096 + k * 256 + t;
-      const double gx = (tile[cc + 1] - ox_p * p[k]) - (tile[cc - 1] - ox_m * p[k]);
-      const double gy = (tile[cc + 18] - oy_p * p[k]) - (tile[cc - 18] - oy_m * p[k]);
-      const double zp = k < 15 ? p[k < 15 ? k + 1 : 15] - p[k] : zhi - oz_p * p[k];
-      const double zm = k > 0 ? p[k > 0 ? k - 1 : 0] - p[k] : zlo - oz_m * p[k];
+      const double gx = (b[cc + 1] - ox_p * p[k]) - (b[cc - 1] - ox_m * p[k]);
+      const double gy = (b[cc + 18] - oy_p * p[k]) - (b[cc - 18] - oy_m * p[k]);
+      const double zp = k < 15 ? p[k < 15 ? k + 1 : 15] - p[k] : hv[5] - oz_p * p[k];
+      const double zm = k > 0 ? p[k > 0 ? k - 1 : 0] - p[k] : hv[4] - oz_m * p[k];
       if (a.unew[0]) a.unew[0][g] = TF(double(a.ustar[0][g]) - ch * gx);
       if (a.unew[1]) a.unew[1][g] = TF(double(a.ustar[1][g]) - ch * gy);
       if (a.unew[2]) a.unew[2][g] = TF(double(a.ustar[2][g]) - ch * (zp - zm));
