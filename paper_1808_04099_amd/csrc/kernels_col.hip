@@ -197,8 +197,8 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_s
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
-      nb[k] = a.b[g];
-      if (POST) nx[k] = a.x[g];
+      nb[k] = ld_nt(a.b + g);
+      if (POST) nx[k] = ld_nt(a.x + g);
     }
     if (POST) {
 #pragma unroll
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_s
     T q[NL];
     if (dots && a.q_dot) {
 #pragma unroll
-      for (int k = 0; k < NL; ++k) q[k] = a.q_dot[(size_t)ce * C::N3 + k * C::N2 + L.l];
+      for (int k = 0; k < NL; ++k) q[k] = ld_nt(a.q_dot + (size_t)ce * C::N3 + k * C::N2 + L.l);
     }
     for (int sw = 0; sw < a.sweeps; ++sw) {
 #pragma unroll
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_s
     if (c >= 0) {
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
-        a.x[(size_t)c * C::N3 + k * C::N2 + L.l] = x[k];
+        st_nt(a.x + (size_t)c * C::N3 + k * C::N2 + L.l, x[k]);
         if (dots) {
           zr += vol * double(x[k]) * double(bv[k]);
           if (a.q_dot) zq += vol * double(x[k]) * double(q[k]);
@@ -323,8 +323,8 @@ __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
-      nx[k] = a.x[g];
-      nb[k] = a.b[g];
+      nx[k] = ld_nt(a.x + g);
+      nb[k] = ld_nt(a.b + g);
     }
     Slots<NQ> S;
     slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
@@ -405,8 +405,8 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
-      nz[k] = a.z[g];
-      np[k] = a.first ? T(0) : a.p[g];
+      nz[k] = ld_nt(a.z + g);
+      np[k] = a.first ? T(0) : ld_nt(a.p + g);
     }
     Slots<NQ> S;
     slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
@@ -458,8 +458,8 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
       const T qv = (sum - d * x[k]) * ih2;
       if (c >= 0) {
         const size_t g = (size_t)c * C::N3 + k * C::N2 + L.l;
-        a.p[g] = x[k];
-        a.q[g] = qv;
+        st_nt(a.p + g, x[k]);
+        st_nt(a.q + g, qv);
         pq += vol * double(x[k]) * double(qv);
       }
     }
@@ -491,8 +491,8 @@ __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
-      np[k] = a.p ? a.p[g] : 0.0;
-      nb[k] = a.b ? a.b[g] : 0.0;
+      np[k] = a.p ? ld_nt(a.p + g) : 0.0;
+      nb[k] = a.b ? ld_nt(a.b + g) : 0.0;
     }
     Slots<NQ> S;
     slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
       if (c >= 0) {
         if (a.b) bb += vol * bv[k] * bv[k];
         rr += vol * r * r;
-        a.r[(size_t)c * C::N3 + k * C::N2 + L.l] = TO(r * a.rscale);
+        st_nt(a.r + (size_t)c * C::N3 + k * C::N2 + L.l, TO(r * a.rscale));
       }
     }
     __syncthreads();
@@ -572,15 +572,15 @@ __global__ __launch_bounds__(256) void kc_ir(IrArgs<T> a) {
     if (c < 0) continue;
     double p[NL];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) p[k] = a.p[(size_t)c * C::N3 + k * C::N2 + L.l];
+    for (int k = 0; k < NL; ++k) p[k] = ld_nt(a.p + (size_t)c * C::N3 + k * C::N2 + L.l);
     if (a.d) {
       T d[NL];
 #pragma unroll
-      for (int k = 0; k < NL; ++k) d[k] = a.d[(size_t)c * C::N3 + k * C::N2 + L.l];
+      for (int k = 0; k < NL; ++k) d[k] = ld_nt(a.d + (size_t)c * C::N3 + k * C::N2 + L.l);
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
         p[k] += a.dscale * double(d[k]);
-        a.p[(size_t)c * C::N3 + k * C::N2 + L.l] = p[k];
+        st_nt(a.p + (size_t)c * C::N3 + k * C::N2 + L.l, p[k]);
       }
     }
     export_col<NL, double>(a.pf_out, c, p, L.i, L.j);
@@ -614,11 +614,11 @@ __global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const size_t g = (size_t)c * 4096 + (k0 + kk) * 256 + t;
-        const TF al = a.alpha ? a.alpha[g] : TF(0);
+        const TF al = a.alpha ? ld_nt(a.alpha + g) : TF(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const TF ut = a.u[d][g];
-          const TF us = a.us[d] ? a.us[d][g] : TF(a.usc[d]);
+          const TF ut = ld_nt(a.u[d] + g);
+          const TF us = a.us[d] ? ld_nt(a.us[d] + g) : TF(a.usc[d]);
           v[d][kk] = a.alpha ? (TF(1) - al) * ut + al * us : ut;
         }
       }
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
         const int k = k0 + kk;
         const size_t g = (size_t)c * 4096 + k * 256 + t;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) a.ustar[d][g] = v[d][kk];
+        for (int d = 0; d < 3; ++d) st_nt(a.ustar[d] + g, v[d][kk]);
         if (i == 0) base[0 * 256 + k * 16 + j] = v[0][kk];
         if (i == 15) base[1 * 256 + k * 16 + j] = v[0][kk];
         if (j == 0) base[2 * 256 + k * 16 + i] = v[1][kk];
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
     {
       TF v[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = a.ustar[2][(size_t)c * 4096 + k * 256 + t];
+      for (int k = 0; k < 16; ++k) v[k] = ld_nt(a.ustar[2] + (size_t)c * 4096 + k * 256 + t);
       double lo, hi;  // face velocities on the -z and +z faces of the column
       {
         const int k4 = m.kind[4], k5 = m.kind[5];
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
       TF v[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        v[k] = a.ustar[d][(size_t)c * 4096 + k * 256 + t];
+        v[k] = ld_nt(a.ustar[d] + (size_t)c * 4096 + k * 256 + t);
         tile[tix16(i, j, k)] = v[k];
       }
 #pragma unroll
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
       __syncthreads();
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) a.b[(size_t)c * 4096 + k * 256 + t] = acc[k] * ih * a.inv_c;
+    for (int k = 0; k < 16; ++k) st_nt(a.b + (size_t)c * 4096 + k * 256 + t, acc[k] * ih * a.inv_c);
   }
 }
 
@@ -728,7 +728,7 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) rf[f][q] = a.pf[S.fine[f][q]];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) p[k] = a.p[(size_t)c * 4096 + k * 256 + t];
+    for (int k = 0; k < 16; ++k) p[k] = ld_nt(a.p + (size_t)c * 4096 + k * 256 + t);
 #pragma unroll
     for (int f = 0; f < 6; ++f) hv[f] = halo_val<double, NQ>(S.kind[f], rf[f]);
     const double ch = a.c * 0.5 / m.h;
@@ -754,9 +754,9 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
       const double gy = (b[cc + 18] - oy_p * p[k]) - (b[cc - 18] - oy_m * p[k]);
       const double zp = k < 15 ? p[k < 15 ? k + 1 : 15] - p[k] : hv[5] - oz_p * p[k];
       const double zm = k > 0 ? p[k > 0 ? k - 1 : 0] - p[k] : hv[4] - oz_m * p[k];
-      if (a.unew[0]) a.unew[0][g] = TF(double(a.ustar[0][g]) - ch * gx);
-      if (a.unew[1]) a.unew[1][g] = TF(double(a.ustar[1][g]) - ch * gy);
-      if (a.unew[2]) a.unew[2][g] = TF(double(a.ustar[2][g]) - ch * (zp - zm));
+      if (a.unew[0]) st_nt(a.unew[0] + g, TF(double(ld_nt(a.ustar[0] + g)) - ch * gx));
+      if (a.unew[1]) st_nt(a.unew[1] + g, TF(double(ld_nt(a.ustar[1] + g)) - ch * gy));
+      if (a.unew[2]) st_nt(a.unew[2] + g, TF(double(ld_nt(a.ustar[2] + g)) - ch * (zp - zm)));
     }
     __syncthreads();
   }

@@ -26,6 +26,17 @@ namespace bcm {
 
 constexpr int WG = 256;
 
+// Streaming (non-temporal) global accesses for field values that a kernel reads or writes
+// once: they bypass the cache retention that face slabs and scalars benefit from.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 template <int NL>
 struct Lv {
   static constexpr int N = NL, N2 = NL * NL, N3 = NL * NL * NL;
