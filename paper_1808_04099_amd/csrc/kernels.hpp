@@ -69,6 +69,7 @@ struct UpdateArgs {     // x += alpha p; r -= alpha q; <r, r>_V
   const T* q;
   const Scalars* sc;
   double* part;
+  int x_zero;           // x starts at zero (not read)
 };
 
 template <typename TO>

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   const size_t base = (size_t)c * a.n3;
   for (int e = threadIdx.x; e < a.n3; e += WG) {
     const size_t g = base + e;
-    st_nt(a.x + g, ld_nt(a.x + g) + al * ld_nt(a.p + g));
+    st_nt(a.x + g, (a.x_zero ? T(0) : ld_nt(a.x + g)) + al * ld_nt(a.p + g));
     const T rv = ld_nt(a.r + g) - al * ld_nt(a.q + g);
     st_nt(a.r + g, rv);
     rr += double(rv) * double(rv);

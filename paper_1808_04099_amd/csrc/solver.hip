@@ -246,10 +246,11 @@ struct SolveLog {
 };
 
 // Flexible CG (or plain V-cycle iteration) on A x = r0 with r (= P->o_r) holding the initial
-// residual and x the accumulator.  Stops when the V-weighted <r, r> <= thr (recurrence).
+// residual and x the accumulator (x_zero: x starts at zero and is not read before its first
+// update).  Stops when the V-weighted <r, r> <= thr (recurrence).
 // hist_scale converts sqrt(<r,r>) to the reported relative residual.
 template <typename T>
-int krylov(bcm_plan* P, T* x, double thr, int max_iter, double hist_scale, SolveLog& log,
+int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist_scale, SolveLog& log,
            Scalars* hs, hipStream_t s) {
   const int NL = P->n;
   const int nparts = partials_of(NL, P->nc);
@@ -272,7 +273,7 @@ int krylov(bcm_plan* P, T* x, double thr, int max_iter, double hist_scale, Solve
       if ((st = finalize(P, OP_PQ, 0, -1, nparts, 0, s))) return st;  // alpha = zr / zr
     }
     UpdateArgs<T> ua{P->at<const CubeMeta>(P->o_meta), P->nc, NL * NL * NL, x, p, r, q,
-                     P->at<const Scalars>(P->o_sc), P->at<double>(P->o_part[0])};
+                     P->at<const Scalars>(P->o_sc), P->at<double>(P->o_part[0]), x_zero && it == 0};
     HIPCHK(timed(P, cls_of("update", 0), s, [&] { return launch_update<T>(ua, s); }), "k_update");
     if ((st = finalize(P, OP_RR, 0, -1, P->nc, 0, s))) return st;
     if ((st = read_scalars(P, hs, s))) return st;
@@ -340,7 +341,7 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
         break;
       }
       if (log.iters >= o.max_iter) break;
-      if ((st = krylov<double>(P, p, tol2 * bb * 0.25, o.max_iter - log.iters, 1.0 / std::sqrt(bb),
+      if ((st = krylov<double>(P, p, false, tol2 * bb * 0.25, o.max_iter - log.iters, 1.0 / std::sqrt(bb),
                                log, &hs, s)))
         return st;
     }
@@ -379,13 +380,12 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
         if ((st = residual64<float>(P, pg, b, r32, rscale, s, faces_ok))) return st;
       }
       float* d = P->at<float>(P->o_d);
-      HIPCHK(fill<float>(d, P->cells, s), "zero fill");
       // reduce the residual by inner_tol, or only by what is still missing to reach tol
       // (with a factor 0.3 of margin), whichever is the weaker requirement
       const double need = 0.3 * o.tol * std::sqrt(bb / rr);
       const double red_target = std::max(o.inner_tol, std::min(need, 0.1));
       const double thr = red_target * red_target * rr * rscale * rscale;
-      if ((st = krylov<float>(P, d, thr, o.max_iter, 1.0 / (rscale * std::sqrt(bb)), log, &hs, s)))
+      if ((st = krylov<float>(P, d, true, thr, o.max_iter, 1.0 / (rscale * std::sqrt(bb)), log, &hs, s)))
         return st;
       IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale};
       HIPCHK(timed(P, cls_of("ir", 0), s, [&] { return launch_ir<float>(P->n, ia, s); }), "k_ir");

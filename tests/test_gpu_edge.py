@@ -1,0 +1,113 @@
+"""GPU edge cases through the C ABI: degenerate inputs, the smallest meshes, ragged workgroup
+units, warm starts and error paths, each against the FP64 oracle where there is a result.
+
+Ragged units: the column kernels give a workgroup 256 / n^2 cubes at n < 16 and take them
+8 launch-table positions apart, so cube counts that are not multiples of 8 * (cubes per
+workgroup) leave empty slots in the last units.
+"""
+import numpy as np
+import pytest
+import torch
+
+from bcm_inputs import CHANNEL_BC, OPEN_BC, uniform_mesh, uniform_random_velocity
+from oracle import FVMesh, projection as OP
+
+from gpu_util import dev, host, log, plan_for, rel_err, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_zero_right_hand_side_gives_zero_pressure(precision):
+    m = uniform_mesh((2, 2, 1), 0.5, 8, CHANNEL_BC)
+    plan = plan_for(m, precision)
+    p0 = dev(np.random.default_rng(1).standard_normal(m.n_cells))  # a guess to be discarded
+    p, rep = plan.poisson_solve(dev(np.zeros(m.n_cells)), p=p0, use_guess=True)
+    assert rep.status == 0 and rep.final_rel_res == 0.0
+    assert np.array_equal(host(p), np.zeros(m.n_cells))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_non_finite_right_hand_side_is_an_error(precision):
+    from paper_1808_04099_amd.api import BCMError
+    m = uniform_mesh((2, 1, 1), 0.5, 8, CHANNEL_BC)
+    plan = plan_for(m, precision)
+    b = np.random.default_rng(2).standard_normal(m.n_cells)
+    b[77] = np.nan
+    with pytest.raises(BCMError) as e:
+        plan.poisson_solve(dev(b))
+    assert e.value.status == -4  # BCM_ERR_NONFINITE
+
+
+def test_invalid_time_step_is_rejected_before_any_work():
+    from paper_1808_04099_amd.api import BCMError
+    m = uniform_mesh((1, 1, 1), 1.0, 4, OPEN_BC)
+    plan = plan_for(m)
+    u = [dev(np.zeros(m.n_cells)) for _ in range(3)]
+    with pytest.raises(BCMError) as e:
+        plan.project(u, None, 1.0, 0.0, 1.0)
+    assert e.value.status == -1  # BCM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_cube(n, precision):
+    """One cube, all faces open: every per-cube level has one (mostly empty) unit."""
+    m = uniform_mesh((1, 1, 1), 1.0, n, OPEN_BC)
+    log(f"single cube n={n} {precision}")
+    fv = FVMesh(m)
+    b = np.random.default_rng(n).standard_normal(m.n_cells)
+    p, rep = plan_for(m, precision).poisson_solve(dev(b))
+    p = host(p)
+    assert rep.status == 0 and fv.residual_norm(p, b) <= 1.2e-10
+    assert rel_err(p, fv.solve(b)) <= 1e-7
+
+
+@pytest.mark.parametrize("dims,n", [((5, 3, 1), 8), ((7, 1, 1), 4), ((3, 3, 3), 2),
+                                    ((3, 1, 1), 16)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_f32fields"])
+def test_ragged_units_projection(dims, n, precision):
+    m = uniform_mesh(dims, 0.25, n, CHANNEL_BC)
+    log(f"ragged {dims} n={n} {precision}: {m.n_cubes} cubes")
+    rng = np.random.default_rng(sum(dims) + n)
+    u = uniform_random_velocity(m, 3, 0.2, (1.0, 0.0, 0.0))
+    alpha = rng.uniform(0.0, 1.0, m.n_cells)
+    f32 = precision == "mixed_f32fields"
+    if f32:
+        u = u.astype(np.float32).astype(np.float64)
+        alpha = alpha.astype(np.float32).astype(np.float64)
+    fv = FVMesh(m)
+    ref = OP.project(fv, u, alpha, (0.0, 0.0, 0.0), 1.0, 0.01, 1.0)
+    plan = plan_for(m, precision)
+    ft = plan.field_dtype
+    out = plan.project([dev(u[d], ft) for d in range(3)], dev(alpha, ft), 1.0, 0.01, 1.0,
+                       want_b=True)
+    p, b = host(out["p"]), host(out["b"])
+    assert out["report"].status == 0 and fv.residual_norm(p, b) <= 1.2e-10
+    unew = np.stack([host(x) for x in out["u_new"]])
+    assert rel_err(unew, ref["u_new"]) <= (1e-5 if f32 else 1e-7)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_warm_start_from_the_solution_needs_no_iteration(precision):
+    m = uniform_mesh((2, 2, 2), 0.5, 8, CHANNEL_BC)
+    fv = FVMesh(m)
+    b = np.random.default_rng(4).standard_normal(m.n_cells)
+    exact = fv.solve(b)
+    plan = plan_for(m, precision)
+    p, rep = plan.poisson_solve(dev(b), p=dev(exact), use_guess=True)
+    assert rep.status == 0 and rep.n_inner == 0
+    assert np.array_equal(host(p), exact)
+
+
+def test_alpha_one_sets_the_body_velocity_before_projection():
+    """alpha = 1 in every cell: u* = u_s everywhere, and a constant u_s along the channel
+    with U_in = u_s,x is already divergence free, so the projection returns it unchanged."""
+    m = uniform_mesh((2, 1, 1), 0.5, 8, CHANNEL_BC)
+    plan = plan_for(m)
+    u = uniform_random_velocity(m, 8, 1.0)
+    out = plan.project([dev(u[d]) for d in range(3)], dev(np.ones(m.n_cells)), 0.7, 0.01, 1.0,
+                       us=(0.7, 0.0, 0.0))
+    unew = np.stack([host(x) for x in out["u_new"]])
+    assert np.abs(unew[0] - 0.7).max() <= 1e-12 and np.abs(unew[1:]).max() <= 1e-12
+    assert np.abs(host(out["p"])).max() <= 1e-12
