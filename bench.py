@@ -104,16 +104,41 @@ def workload(name):
                                           "cells), sphere r=0.15, u=(1,0,0)+0.05U[-1,1]")
     if name == "small_box":
         return configs.small_box(), "small_box: 4x4x4 cubes of 16^3, open box"
+    if name == "multilevel":
+        pr = configs.multilevel()
+        m = pr["mesh"]
+        return pr, (f"multilevel: {m.n_cubes} cubes of 16^3 ({m.n_cells:,} cells) at levels 0-2 "
+                    f"(2:1 faces) on [0,2]x[0,1]^2, inflow/outflow/slip, box + ellipsoid body as "
+                    f"volume fraction, u=(1,0,0)+0.05U[-1,1]")
     raise SystemExit(f"unknown workload {name}")
 
 
 def cpu_baseline(pr, seconds=10.0):
-    """Oracle's 7-point operator on the global array (NumPy, one thread) timed for ~seconds
-    over the full workload, plus one oracle projection (spectral solve, all cores)."""
+    """The oracle timed on this host.  Uniform meshes: its 7-point operator on the global array
+    (NumPy, one thread) applied to the full field for ~seconds, plus one full oracle projection
+    (spectral solve, all cores).  Multi-level meshes: its cell-by-cell operator (pure Python,
+    one thread) on seeded random cells for ~seconds."""
     import numpy as np
+    m = pr["mesh"]
+    if len(set(m.level.tolist())) > 1:
+        from oracle.sample import CellSampler
+        cs = CellSampler(m)
+        p = np.random.default_rng(0).standard_normal(m.n_cells)
+        cells = np.random.default_rng(1).integers(0, m.n_cells, 1 << 20)
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < seconds and done < cells.size:
+            cs.laplacian(p, int(cells[done]))
+            done += 1
+        dt = time.perf_counter() - t0
+        return dict(value=done / dt, unit="cell-updates/s", cores=1, kind="oracle",
+                    sample=(f"{done} seeded random cells of the {m.n_cells}-cell multi-level "
+                            f"mesh, each one application of the oracle's cell-by-cell FP64 "
+                            f"finite-volume operator (pure Python, single thread)"),
+                    oracle_projection_s=None)
     from oracle import UniformGrid
-    ug = UniformGrid(pr["mesh"])
-    g = ug.to_global(np.random.default_rng(0).standard_normal(pr["mesh"].n_cells))
+    ug = UniformGrid(m)
+    g = ug.to_global(np.random.default_rng(0).standard_normal(m.n_cells))
     t0 = time.perf_counter()
     reps = 0
     while True:
@@ -125,10 +150,10 @@ def cpu_baseline(pr, seconds=10.0):
     t1 = time.perf_counter()
     ug.project(pr["u"], pr["alpha"], (0.0, 0.0, 0.0), pr["U_in"], pr["dt"], pr["rho"])
     t_proj = time.perf_counter() - t1
-    return dict(value=pr["mesh"].n_cells / t_apply, unit="cell-updates/s", cores=1,
+    return dict(value=m.n_cells / t_apply, unit="cell-updates/s", cores=1,
                 kind="oracle",
                 sample=(f"{reps} applications of the oracle's FP64 7-point operator (array form, "
-                        f"NumPy, single thread) to the full {pr['mesh'].n_cells}-cell field; "
+                        f"NumPy, single thread) to the full {m.n_cells}-cell field; "
                         f"the oracle's full projection step (exact DCT solve, scipy.fft on "
                         f"{os.cpu_count()} threads) took {t_proj:.2f} s"),
                 oracle_projection_s=t_proj)
@@ -264,9 +289,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mixed_channel")
+    ap.add_argument("--workload", default="mixed_channel",
+                    choices=["mixed_channel", "sphere_channel", "small_box", "multilevel"])
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed_f32fields"])
     ap.add_argument("--kernel", default=None,
+                    choices=["presmooth16", "postsmooth16", "restrict16", "apply16", "update",
+                             "resid64", "ir", "force", "div", "correct"],
                     help="timer class for the roofline (skips the per-class survey)")
     ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
