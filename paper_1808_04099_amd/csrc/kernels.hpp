@@ -7,6 +7,12 @@
 
 namespace bcm {
 
+// Values per cube in the face buffer of a level with NL cells per cube edge: the six face
+// slabs (NL^2 values each, the cube's boundary layer) followed by their 2x2 means ((NL/2)^2
+// values each).  The means are written only for faces that border a coarser cube: that
+// cube's halo takes one value per cell, the mean of the four finer cells facing it.
+__host__ __device__ constexpr int face_stride(int NL) { return 6 * NL * NL + 6 * (NL / 2) * (NL / 2); }
+
 // Device-resident scalars of one Krylov solve (written by k_finalize, read by the kernels).
 struct Scalars {
   double rr, rr0, bb, zr, zq, pq, alpha, beta, gU, spare[7];

@@ -29,7 +29,7 @@ struct Col {
   static constexpr int CPB = NL >= 16 ? 1 : 256 / N2;  // cubes per workgroup
   static constexpr int W = NL + 2, P = W * W, TS = NL * P;  // LDS tile of one cube
   static constexpr int H = NL / 2, H2 = H * H, H3 = H2 * H;  // next coarser per-cube level
-  static constexpr int F = 6 * N2, FH = 6 * H2;  // face-buffer values per cube (this level, next)
+  static constexpr int F = face_stride(NL), FH = face_stride(H);  // face-buffer values per cube
   __device__ static int tix(int s, int i, int j, int k) { return s * TS + k * P + (j + 1) * W + (i + 1); }
   // LDS position of the halo cell of face f (0..3) at tangential position (t1, t2)
   __device__ static int halo(int s, int f, int t1, int t2) {
@@ -66,58 +66,55 @@ __device__ __forceinline__ int unit_cube(const Geom& g, int u, int s) {
   return c;
 }
 
-// Face-buffer offsets of the NQ neighbour values a lane needs on each face (NQ = 1 on
-// single-level meshes, 4 where a face may be covered by four finer cubes).  Same-level and
-// coarser faces repeat one address; domain-boundary faces point at the cube's own slab (a
-// value that staging discards).  Offsets into the face buffer of this level and, for
-// prolongated corrections, into that of the next coarser level.
-template <int NQ>
+// Face-buffer offsets of the neighbour value a lane needs on each face:
+//   same level    -> the neighbour's boundary cell;
+//   coarser (2:1) -> the coarse cell covering this cell's quadrant of the face;
+//   finer (2:1)   -> the 2x2 mean that the finer neighbour exports for this cell;
+//   domain boundary -> the cube's own slab (a value that staging discards).
+// Offsets into the face buffer of this level and, for prolongated corrections, into that of
+// the next coarser level (the four finer cells facing a cell lie in one cell of that level).
 struct Slots {
-  int fine[6][NQ];
-  int coarse[6][NQ];
+  int fine[6];
+  int coarse[6];
   int kind[6];
 };
 
-template <int NL, int NQ>
-__device__ __forceinline__ void slots(const CubeMeta& m, int self, int t1, int t2, Slots<NQ>& S,
-                                      bool coarse) {
+// ML = false: a single-level mesh (only same-level neighbours and domain boundaries).
+template <int NL, bool ML>
+__device__ __forceinline__ void slots(const CubeMeta& m, int self, int t1, int t2, Slots& S) {
   using C = Col<NL>;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int kd = m.kind[f], of = f ^ 1;
     S.kind[f] = kd;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      int c = self, o = f, a = t1, b = t2;
-      if (kd == FK_SAME) {
-        c = m.nbr[f][0];
-        o = of;
-      } else if (kd == FK_COARSER) {
-        const int qd = m.quad[f];
-        c = m.nbr[f][0];
-        o = of;
-        a = (qd & 1) * C::H + (t1 >> 1);
-        b = (qd >> 1) * C::H + (t2 >> 1);
-      } else if (kd == FK_FINER) {
-        const int F1 = 2 * t1 + (q & 1), F2 = 2 * t2 + (q >> 1);
-        c = m.nbr[f][(F1 / NL) + 2 * (F2 / NL)];
-        o = of;
-        a = F1 % NL;
-        b = F2 % NL;
-      }
-      S.fine[f][q] = c * C::F + o * C::N2 + b * NL + a;
-      if (coarse) S.coarse[f][q] = c * C::FH + o * C::H2 + (b >> 1) * C::H + (a >> 1);
+    int fo = self * C::F + f * C::N2 + t2 * NL + t1;
+    int co = self * C::FH + f * C::H2 + (t2 >> 1) * C::H + (t1 >> 1);
+    if (kd == FK_SAME) {
+      const int c = m.nbr[f][0];
+      fo = c * C::F + of * C::N2 + t2 * NL + t1;
+      co = c * C::FH + of * C::H2 + (t2 >> 1) * C::H + (t1 >> 1);
+    } else if (ML && kd == FK_COARSER) {
+      const int qd = m.quad[f], c = m.nbr[f][0];
+      const int a = (qd & 1) * C::H + (t1 >> 1), b = (qd >> 1) * C::H + (t2 >> 1);
+      fo = c * C::F + of * C::N2 + b * NL + a;
+      co = c * C::FH + of * C::H2 + (b >> 1) * C::H + (a >> 1);
+    } else if (ML && kd == FK_FINER) {
+      const int u1 = t1 >= C::H, u2 = t2 >= C::H;
+      const int c = m.nbr[f][u1 + 2 * u2];
+      const int A = t1 - u1 * C::H, B = t2 - u2 * C::H;
+      fo = c * C::F + 6 * C::N2 + of * C::H2 + B * C::H + A;
+      co = c * C::FH + of * C::H2 + B * C::H + A;
     }
+    S.fine[f] = fo;
+    S.coarse[f] = co;
   }
 }
 
-// Scaled halo value of one face from its raw neighbour values (RULE_P).  A select, not a zero
+// Scaled halo value of one face from its raw neighbour value (RULE_P).  A select, not a zero
 // scale: the dummy slab of a boundary face may hold anything.
-template <typename T, int NQ>
-__device__ __forceinline__ T halo_val(int kd, const T (&r)[NQ]) {
-  T s = r[0];
-  if (NQ == 4 && kd == FK_FINER) s = T(0.25) * (((r[0] + r[1]) + r[2]) + r[3]);
-  return kd <= FK_FINER ? T(RuleTab<RULE_P>::nbeff(kd)) * s : T(0);
+template <typename T>
+__device__ __forceinline__ T halo_val(int kd, T r) {
+  return kd <= FK_FINER ? T(RuleTab<RULE_P>::nbeff(kd)) * r : T(0);
 }
 
 // Stage face values: faces 0..3 into the LDS ring at this lane's slot, 4/5 into registers.
@@ -163,6 +160,31 @@ __device__ __forceinline__ void export_col(T* xf, int c, const T (&x)[NL], int i
   base[5 * N2 + j * NL + i] = x[NL - 1];
 }
 
+// 2x2 means of the face slabs on faces that border a coarser cube (see face_stride), from the
+// cube's values in the LDS tile; summed in the order (0,0), (1,0), (0,1), (1,1) of the two
+// tangential axes.  Lanes of each cube slot with l < (NL/2)^2 compute one mean per face.
+template <int NL, typename T>
+__device__ __forceinline__ void export_avg(T* xf, int c, const T* tile, const CubeMeta& m,
+                                           const LaneC<NL>& L) {
+  using C = Col<NL>;
+  if (L.l >= C::H2) return;
+  const int A = L.l % C::H, B = L.l / C::H;
+  T* base = xf + (size_t)c * C::F + 6 * C::N2;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if (m.kind[f] != FK_COARSER) continue;
+    const int lay = (f & 1) ? NL - 1 : 0, d = f >> 1;
+    T v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = 2 * A + (q & 1), b = 2 * B + (q >> 1);
+      const int i = d == 0 ? lay : a, j = d == 0 ? a : (d == 1 ? lay : b), k = d == 2 ? lay : b;
+      v[q] = tile[C::tix(L.s, i, j, k)];
+    }
+    base[f * C::H2 + B * C::H + A] = T(0.25) * (((v[0] + v[1]) + v[2]) + v[3]);
+  }
+}
+
 template <int NL, typename T>
 __device__ __forceinline__ T nbsum(const T* tile, const T (&x)[NL], int k, int c, T zlo, T zhi) {
   constexpr int W = Col<NL>::W;
@@ -181,8 +203,8 @@ __device__ __forceinline__ void zero_tail(double* part, int units) {
 // in black-red order (+ fused <x, b> and <x, q> on the finest level), else smoothing in
 // red-black order from a zero initial guess.
 // ------------------------------------------------------------------------------------------
-template <typename T, int NL, bool POST, int NQ>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
+template <typename T, int NL, bool POST, bool ML>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && !ML) ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
   __shared__ T tile[C::CPB * C::TS];
   __shared__ double red[8];
@@ -191,7 +213,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_s
   const int i = L.i, j = L.j;
   const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
   const bool dots = POST && a.part_zr != nullptr;
-  T nx[NL], nb[NL], nxc[C::H], rf[6][NQ], rc[6][NQ];
+  T nx[NL], nb[NL], nxc[C::H], rf[6], rc[6];
   int kinds[6];
   auto fetch = [&](int cc) {
 #pragma unroll
@@ -204,16 +226,13 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_s
 #pragma unroll
       for (int kk = 0; kk < C::H; ++kk)
         nxc[kk] = a.xc[(size_t)cc * C::H3 + (kk * C::H + (j >> 1)) * C::H + (i >> 1)];
-      Slots<NQ> S;
-      slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, true);
+      Slots S;
+      slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
         kinds[f] = S.kind[f];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          rf[f][q] = a.xf_in[S.fine[f][q]];
-          rc[f][q] = a.xcf[S.coarse[f][q]];
-        }
+        rf[f] = a.xf_in[S.fine[f]];
+        rc[f] = a.xcf[S.coarse[f]];
       }
     }
   };
@@ -235,12 +254,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_s
     if (POST) {
       T hv[6];
 #pragma unroll
-      for (int f = 0; f < 6; ++f) {
-        T r[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) r[q] = rf[f][q] + rc[f][q];
-        hv[f] = halo_val<T, NQ>(kinds[f], r);
-      }
+      for (int f = 0; f < 6; ++f) hv[f] = halo_val<T>(kinds[f], rf[f] + rc[f]);
       stage<NL, T>(tile, hv, L, zlo, zhi);
     } else {
 #pragma unroll
@@ -288,7 +302,9 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_s
         }
       }
       export_col<NL, T>(a.xf_out, c, x, i, j);
+      if (ML) export_avg<NL, T>(a.xf_out, c, tile, m, L);
     }
+    if (ML) __syncthreads();  // the means read the tile the next cube overwrites
     u = un;
     c = cn;
   }
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && NQ == 1) ? 3 : 1) void kc_s
 }
 
 // Residual of x and restriction to the next level (mean of the 8 children).
-template <typename T, int NL, int NQ>
+template <typename T, int NL, bool ML>
 __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
   using C = Col<NL>;
   __shared__ T tile[C::CPB * C::TS];
@@ -317,7 +333,7 @@ __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
   const LaneC<NL> L(t);
   const int i = L.i, j = L.j;
   const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
-  T nx[NL], nb[NL], rf[6][NQ];
+  T nx[NL], nb[NL], rf[6];
   int kinds[6];
   auto fetch = [&](int cc) {
 #pragma unroll
@@ -326,13 +342,12 @@ __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
       nx[k] = ld_nt(a.x + g);
       nb[k] = ld_nt(a.b + g);
     }
-    Slots<NQ> S;
-    slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
+    Slots S;
+    slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       kinds[f] = S.kind[f];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) rf[f][q] = a.xf[S.fine[f][q]];
+      rf[f] = a.xf[S.fine[f]];
     }
   };
   int u = blockIdx.x;
@@ -350,7 +365,7 @@ __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
       tile[C::tix(L.s, i, j, k)] = x[k];
     }
 #pragma unroll
-    for (int f = 0; f < 6; ++f) hv[f] = halo_val<T, NQ>(kinds[f], rf[f]);
+    for (int f = 0; f < 6; ++f) hv[f] = halo_val<T>(kinds[f], rf[f]);
     stage<NL, T>(tile, hv, L, zlo, zhi);
     const T h = T(m.h * a.g.hscale);
     const T ih2 = T(1) / (h * h);
@@ -389,7 +404,7 @@ __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
 }
 
 // p = z + beta p (or z); q = A p; partial <p, q>_V.
-template <typename T, int NL, int NQ>
+template <typename T, int NL, bool ML>
 __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   using C = Col<NL>;
   __shared__ T tile[C::CPB * C::TS];
@@ -399,7 +414,7 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   const int i = L.i, j = L.j;
   const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
   const T beta = a.first ? T(0) : T(a.sc->beta);
-  T nz[NL], np[NL], rz[6][NQ], rp[6][NQ];
+  T nz[NL], np[NL], rz[6], rp[6];
   int kinds[6];
   auto fetch = [&](int cc) {
 #pragma unroll
@@ -408,16 +423,13 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
       nz[k] = ld_nt(a.z + g);
       np[k] = a.first ? T(0) : ld_nt(a.p + g);
     }
-    Slots<NQ> S;
-    slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
+    Slots S;
+    slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       kinds[f] = S.kind[f];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        rz[f][q] = a.zf[S.fine[f][q]];
-        rp[f][q] = a.first ? T(0) : a.pf_in[S.fine[f][q]];
-      }
+      rz[f] = a.zf[S.fine[f]];
+      rp[f] = a.first ? T(0) : a.pf_in[S.fine[f]];
     }
   };
   int u = blockIdx.x;
@@ -435,12 +447,7 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
       tile[C::tix(L.s, i, j, k)] = x[k];
     }
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      T r[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) r[q] = rz[f][q] + beta * rp[f][q];
-      hv[f] = halo_val<T, NQ>(kinds[f], r);
-    }
+    for (int f = 0; f < 6; ++f) hv[f] = halo_val<T>(kinds[f], rz[f] + beta * rp[f]);
     stage<NL, T>(tile, hv, L, zlo, zhi);
     const T h = T(m.h * a.g.hscale);
     const T ih2 = T(1) / (h * h);
@@ -463,7 +470,10 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
         pq += vol * double(x[k]) * double(qv);
       }
     }
-    if (c >= 0) export_col<NL, T>(a.pf_out, c, x, i, j);
+    if (c >= 0) {
+      export_col<NL, T>(a.pf_out, c, x, i, j);
+      if (ML) export_avg<NL, T>(a.pf_out, c, tile, m, L);
+    }
     __syncthreads();
     u = un;
     c = cn;
@@ -476,7 +486,7 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
 }
 
 // r = b - A p in FP64 (p may be nullptr = 0; b may be nullptr -> r = A p), stored as TO * rscale.
-template <typename TO, int NL, int NQ>
+template <typename TO, int NL, bool ML>
 __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
   using C = Col<NL>;
   __shared__ double tile[C::CPB * C::TS];
@@ -485,7 +495,7 @@ __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
   const LaneC<NL> L(t);
   const int i = L.i, j = L.j;
   const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
-  double np[NL], nb[NL], rf[6][NQ];
+  double np[NL], nb[NL], rf[6];
   int kinds[6];
   auto fetch = [&](int cc) {
 #pragma unroll
@@ -494,13 +504,12 @@ __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
       np[k] = a.p ? ld_nt(a.p + g) : 0.0;
       nb[k] = a.b ? ld_nt(a.b + g) : 0.0;
     }
-    Slots<NQ> S;
-    slots<NL, NQ>(a.g.meta[cc], cc, i, j, S, false);
+    Slots S;
+    slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       kinds[f] = S.kind[f];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) rf[f][q] = a.p ? a.pf[S.fine[f][q]] : 0.0;
+      rf[f] = a.p ? a.pf[S.fine[f]] : 0.0;
     }
   };
   int u = blockIdx.x;
@@ -519,7 +528,7 @@ __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
       tile[C::tix(L.s, i, j, k)] = x[k];
     }
 #pragma unroll
-    for (int f = 0; f < 6; ++f) hv[f] = halo_val<double, NQ>(kinds[f], rf[f]);
+    for (int f = 0; f < 6; ++f) hv[f] = halo_val<double>(kinds[f], rf[f]);
     stage<NL, double>(tile, hv, L, zlo, zhi);
     const double h = m.h * a.g.hscale;
     const double ih2 = 1.0 / (h * h);
@@ -561,29 +570,38 @@ __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
   }
 }
 
-// p += dscale d (when d is given) in FP64; export the faces of p.
-template <typename T, int NL>
+// p += dscale d (when d is given) in FP64; export the faces of p (ML: and their 2x2 means,
+// staged through LDS).
+template <typename T, int NL, bool ML>
 __global__ __launch_bounds__(256) void kc_ir(IrArgs<T> a) {
   using C = Col<NL>;
+  __shared__ double tile[ML ? C::CPB * C::TS : 1];
   const LaneC<NL> L(threadIdx.x);
   const int U = col_units(C::CPB, a.g.n_cubes);
   for (int u = blockIdx.x; u < U; u += gridDim.x) {
     const int c = unit_cube<NL>(a.g, u, L.s);
-    if (c < 0) continue;
+    const int ce = c < 0 ? 0 : c;
     double p[NL];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) p[k] = ld_nt(a.p + (size_t)c * C::N3 + k * C::N2 + L.l);
+    for (int k = 0; k < NL; ++k) p[k] = ld_nt(a.p + (size_t)ce * C::N3 + k * C::N2 + L.l);
     if (a.d) {
       T d[NL];
 #pragma unroll
-      for (int k = 0; k < NL; ++k) d[k] = ld_nt(a.d + (size_t)c * C::N3 + k * C::N2 + L.l);
+      for (int k = 0; k < NL; ++k) d[k] = ld_nt(a.d + (size_t)ce * C::N3 + k * C::N2 + L.l);
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
         p[k] += a.dscale * double(d[k]);
-        st_nt(a.p + (size_t)c * C::N3 + k * C::N2 + L.l, p[k]);
+        if (c >= 0) st_nt(a.p + (size_t)c * C::N3 + k * C::N2 + L.l, p[k]);
       }
     }
-    export_col<NL, double>(a.pf_out, c, p, L.i, L.j);
+    if (c >= 0) export_col<NL, double>(a.pf_out, c, p, L.i, L.j);
+    if (ML) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) tile[C::tix(L.s, L.i, L.j, k)] = p[k];
+      __syncthreads();
+      if (c >= 0) export_avg<NL, double>(a.pf_out, c, tile, a.g.meta[c], L);
+      __syncthreads();
+    }
   }
 }
 
@@ -596,7 +614,7 @@ __device__ __forceinline__ int halo16(int f, int t) { return Col<16>::halo(0, f,
 
 template <typename T>
 __device__ __forceinline__ T face_get(const T* f, int c, int of, int t1, int t2) {
-  return f[(size_t)c * 1536 + of * 256 + t2 * 16 + t1];
+  return f[(size_t)c * Col<16>::F + of * 256 + t2 * 16 + t1];
 }
 
 // u* = (1 - alpha) u~ + alpha u_s, and the face-normal component of u* on each face.  A pure
@@ -607,7 +625,7 @@ __global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
   const int n = a.g.n_cubes;
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
     const int c = a.g.launch[w];
-    TF* base = a.uf + (size_t)c * 1536;
+    TF* base = a.uf + (size_t)c * Col<16>::F;
 #pragma unroll 1
     for (int k0 = 0; k0 < 16; k0 += 4) {
       TF v[3][4];
@@ -712,7 +730,7 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
 // x/y neighbours of p go through LDS one plane at a time (two plane buffers used in turn);
 // the halo ring of plane k comes from the lanes with j == k, which hold the x/y face values
 // at z = k (tangential position (t1, t2) = (i, j) of faces 0..3).
-template <typename TF, int NQ>
+template <typename TF, bool ML>
 __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
   __shared__ double pl[2][P16];
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
@@ -720,17 +738,15 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
     const int c = a.g.launch[w];
     const CubeMeta& m = a.g.meta[c];
-    double p[16], hv[6], rf[6][NQ];
-    Slots<NQ> S;
-    slots<16, NQ>(m, c, i, j, S, false);
+    double p[16], hv[6], rf[6];
+    Slots S;
+    slots<16, ML>(m, c, i, j, S);
 #pragma unroll
-    for (int f = 0; f < 6; ++f)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) rf[f][q] = a.pf[S.fine[f][q]];
+    for (int f = 0; f < 6; ++f) rf[f] = a.pf[S.fine[f]];
 #pragma unroll
     for (int k = 0; k < 16; ++k) p[k] = ld_nt(a.p + (size_t)c * 4096 + k * 256 + t);
 #pragma unroll
-    for (int f = 0; f < 6; ++f) hv[f] = halo_val<double, NQ>(S.kind[f], rf[f]);
+    for (int f = 0; f < 6; ++f) hv[f] = halo_val<double>(S.kind[f], rf[f]);
     const double ch = a.c * 0.5 / m.h;
     const double ox_m = i == 0 ? RuleTab<RULE_P>::own(m.kind[0]) : 1.0;
     const double ox_p = i == 15 ? RuleTab<RULE_P>::own(m.kind[1]) : 1.0;
@@ -802,36 +818,36 @@ template <typename T>
 hipError_t launchc_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s) {
   BCM_COL_NL(NL, {
     constexpr int cpb = Col<NLC>::CPB;
-    if (a.zero_init) return launch_col(kc_smooth<T, NLC, false, 1>, cpb, a, s);
-    if (a.g.multilevel) return launch_col(kc_smooth<T, NLC, true, 4>, cpb, a, s);
-    return launch_col(kc_smooth<T, NLC, true, 1>, cpb, a, s);
+    if (a.g.multilevel) {
+      if (a.zero_init) return launch_col(kc_smooth<T, NLC, false, true>, cpb, a, s);
+      return launch_col(kc_smooth<T, NLC, true, true>, cpb, a, s);
+    }
+    if (a.zero_init) return launch_col(kc_smooth<T, NLC, false, false>, cpb, a, s);
+    return launch_col(kc_smooth<T, NLC, true, false>, cpb, a, s);
   });
   return hipSuccess;
 }
 template <typename T>
 hipError_t launchc_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s) {
   BCM_COL_NL(NL, {
-    constexpr int cpb = Col<NLC>::CPB;
-    if (a.g.multilevel) return launch_col(kc_restrict<T, NLC, 4>, cpb, a, s);
-    return launch_col(kc_restrict<T, NLC, 1>, cpb, a, s);
+    if (a.g.multilevel) return launch_col(kc_restrict<T, NLC, true>, Col<NLC>::CPB, a, s);
+    return launch_col(kc_restrict<T, NLC, false>, Col<NLC>::CPB, a, s);
   });
   return hipSuccess;
 }
 template <typename T>
 hipError_t launchc_apply(int NL, const ApplyArgs<T>& a, hipStream_t s) {
   BCM_COL_NL(NL, {
-    constexpr int cpb = Col<NLC>::CPB;
-    if (a.g.multilevel) return launch_col(kc_apply<T, NLC, 4>, cpb, a, s);
-    return launch_col(kc_apply<T, NLC, 1>, cpb, a, s);
+    if (a.g.multilevel) return launch_col(kc_apply<T, NLC, true>, Col<NLC>::CPB, a, s);
+    return launch_col(kc_apply<T, NLC, false>, Col<NLC>::CPB, a, s);
   });
   return hipSuccess;
 }
 template <typename TO>
 hipError_t launchc_resid64(int NL, const Resid64Args<TO>& a, hipStream_t s) {
   BCM_COL_NL(NL, {
-    constexpr int cpb = Col<NLC>::CPB;
-    if (a.g.multilevel) return launch_col(kc_resid64<TO, NLC, 4>, cpb, a, s);
-    return launch_col(kc_resid64<TO, NLC, 1>, cpb, a, s);
+    if (a.g.multilevel) return launch_col(kc_resid64<TO, NLC, true>, Col<NLC>::CPB, a, s);
+    return launch_col(kc_resid64<TO, NLC, false>, Col<NLC>::CPB, a, s);
   });
   return hipSuccess;
 }
@@ -839,7 +855,10 @@ template <typename T>
 hipError_t launchc_ir(int NL, const IrArgs<T>& a, hipStream_t s) {
   BCM_COL_NL(NL, {
     const int units = col_units(Col<NLC>::CPB, a.g.n_cubes);
-    hipLaunchKernelGGL((kc_ir<T, NLC>), dim3(std::min(units, 4096)), dim3(256), 0, s, a);
+    if (a.g.multilevel)
+      hipLaunchKernelGGL((kc_ir<T, NLC, true>), dim3(std::min(units, 4096)), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((kc_ir<T, NLC, false>), dim3(std::min(units, 4096)), dim3(256), 0, s, a);
     return hipGetLastError();
   });
   return hipSuccess;
@@ -857,9 +876,9 @@ hipError_t launch16_div(const DivArgs<TF>& a, hipStream_t s) {
 template <typename TF>
 hipError_t launch16_correct(const CorrectArgs<TF>& a, hipStream_t s) {
   if (a.g.multilevel)
-    hipLaunchKernelGGL((k16_correct<TF, 4>), dim3(std::min(a.g.n_cubes, 2048)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k16_correct<TF, true>), dim3(std::min(a.g.n_cubes, 2048)), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k16_correct<TF, 1>), dim3(std::min(a.g.n_cubes, 2048)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k16_correct<TF, false>), dim3(std::min(a.g.n_cubes, 2048)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

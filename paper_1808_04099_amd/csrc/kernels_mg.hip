@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_export(ExportArgs<T, TO> a) {
       if (cube[s] < 0 || (a.comp_faces && (f >> 1) != d)) continue;
       int i, j, k;
       face_cell<NL>(f, t % NL, t / NL, i, j, k);
-      a.xf[(size_t)cube[s] * 6 * L::N2 + r] = TO(tile[s * L::TILE + ti<NL>(i, j, k)]);
+      a.xf[(size_t)cube[s] * L::FACE + r] = TO(tile[s * L::TILE + ti<NL>(i, j, k)]);
     }
     __syncthreads();
   }
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
     const T v = T(xv[c]);
     a.x[c] = v;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) a.xf[(size_t)c * 6 + f] = v;
+    for (int f = 0; f < 6; ++f) a.xf[(size_t)c * face_stride(1) + f] = v;
   }
 }
 
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
     const T v = lv[0].x[a.perm0[c]];
     a.x_out[c] = v;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) a.xf_out[(size_t)c * 6 + f] = v;
+    for (int f = 0; f < 6; ++f) a.xf_out[(size_t)c * face_stride(1) + f] = v;
   }
 }
 

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs<TF> a) {
       if (cube[s] < 0) continue;
       int i, j, k;
       face_cell<NL>(f, t % NL, t / NL, i, j, k);
-      a.uf[(size_t)cube[s] * 6 * L::N2 + f * L::N2 + t] = tile[s * L::TILE + ti<NL>(i, j, k)];
+      a.uf[(size_t)cube[s] * L::FACE + f * L::N2 + t] = tile[s * L::TILE + ti<NL>(i, j, k)];
     }
     __syncthreads();
   }

@@ -639,7 +639,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   P->inner32 = o.precision != BCM_FP64;
   P->fields32 = o.precision == BCM_MIXED_F32FIELDS;
   const size_t Ti = P->inner32 ? 4 : 8, Tf = P->fields32 ? 4 : 8;
-  const size_t nc = size_t(M.n_cubes), n2 = size_t(M.n) * M.n, cells = P->cells;
+  const size_t nc = size_t(M.n_cubes), cells = P->cells;
   size_t top = 0;
   P->o_meta = take(top, nc * sizeof(CubeMeta));
   P->o_launch = take(top, nc * sizeof(int32_t));
@@ -648,9 +648,9 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   P->o_sc = take(top, sizeof(Scalars));
   P->o_cw = take(top, 4 * nc * sizeof(double));
   for (int d = 0; d < 3; ++d) P->o_ustar[d] = take(top, cells * Tf);
-  P->o_uf = take(top, 6 * n2 * nc * Tf);
+  P->o_uf = take(top, size_t(face_stride(M.n)) * nc * Tf);
   P->o_b64 = take(top, cells * 8);
-  P->o_pf = take(top, 6 * n2 * nc * 8);
+  P->o_pf = take(top, size_t(face_stride(M.n)) * nc * 8);
   P->o_lam = take(top, cells * 8);
   P->o_r = take(top, cells * Ti);
   P->o_z = take(top, cells * Ti);
@@ -658,8 +658,8 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   P->o_q = take(top, cells * Ti);
   P->o_d = P->inner32 ? take(top, cells * 4) : 0;
   for (int i = 0; i < 2; ++i) {
-    P->o_zf[i] = take(top, 6 * n2 * nc * Ti);
-    P->o_pfk[i] = take(top, 6 * n2 * nc * Ti);
+    P->o_zf[i] = take(top, size_t(face_stride(M.n)) * nc * Ti);
+    P->o_pfk[i] = take(top, size_t(face_stride(M.n)) * nc * Ti);
   }
   P->o_x.assign(P->nlev, 0);
   P->o_b.assign(P->nlev, 0);
@@ -669,8 +669,8 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
     const size_t NL = size_t(M.n >> l);
     P->o_x[l] = take(top, nc * NL * NL * NL * Ti);
     P->o_b[l] = take(top, nc * NL * NL * NL * Ti);
-    P->o_xf[0][l] = take(top, 6 * NL * NL * nc * Ti);
-    P->o_xf[1][l] = take(top, 6 * NL * NL * nc * Ti);
+    P->o_xf[0][l] = take(top, size_t(face_stride(int(NL))) * nc * Ti);
+    P->o_xf[1][l] = take(top, size_t(face_stride(int(NL))) * nc * Ti);
   }
   P->graph = o.coarse_solver == 1 && M.coarse.ok && !M.coarse.levels.empty();
   if (P->graph) {

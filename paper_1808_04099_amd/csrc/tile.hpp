@@ -42,7 +42,7 @@ struct Lv {
   static constexpr int N = NL, N2 = NL * NL, N3 = NL * NL * NL;
   static constexpr int T = NL + 2, T2 = T * T, TILE = T * T * T;
   static constexpr int CPB = (N3 >= WG) ? 1 : WG / N3;  // cubes per workgroup
-  static constexpr int FACE = 6 * N2;                   // face-buffer values per cube
+  static constexpr int FACE = face_stride(NL);          // face-buffer values per cube
 };
 
 template <int NL>
@@ -214,7 +214,7 @@ __device__ __forceinline__ void export_faces(TO* faces, const T* tile, const int
     if (cube[s] < 0) continue;
     int i, j, k;
     face_cell<NL>(f, t % NL, t / NL, i, j, k);
-    faces[(size_t)cube[s] * 6 * N2 + r] = TO(tile[s * TILE + ti<NL>(i, j, k)]);
+    faces[(size_t)cube[s] * Lv<NL>::FACE + r] = TO(tile[s * TILE + ti<NL>(i, j, k)]);
   }
 }
 
@@ -236,29 +236,7 @@ template <int NL, typename T>
 struct FaceGet {
   const T* f;
   __device__ T operator()(int c, int of, int t1, int t2) const {
-    return f[(size_t)c * 6 * NL * NL + of * NL * NL + t2 * NL + t1];
-  }
-};
-
-template <int NL, typename T>
-struct FaceGetAxpy {  // a + beta * b
-  const T* a;
-  const T* b;
-  T beta;
-  __device__ T operator()(int c, int of, int t1, int t2) const {
-    const size_t o = (size_t)c * 6 * NL * NL + of * NL * NL + t2 * NL + t1;
-    return a[o] + beta * b[o];
-  }
-};
-
-template <int NL, typename T>
-struct FaceGetProlong {  // fine face value (or 0) + coarse face value of the covering coarse cell
-  const T* f;
-  const T* fc;
-  __device__ T operator()(int c, int of, int t1, int t2) const {
-    constexpr int NC = NL / 2;
-    T v = f ? f[(size_t)c * 6 * NL * NL + of * NL * NL + t2 * NL + t1] : T(0);
-    return v + fc[(size_t)c * 6 * NC * NC + of * NC * NC + (t2 >> 1) * NC + (t1 >> 1)];
+    return f[(size_t)c * face_stride(NL) + of * NL * NL + t2 * NL + t1];
   }
 };
 
