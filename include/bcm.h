@@ -111,7 +111,10 @@ typedef struct {
   int32_t coarse_solver;/* one-cell-per-cube level: 0 = CG only (the paper's scheme),
                            1 = multigrid on the cube graph (octree, then lattice merging;
                            box-shaped domains, otherwise 0 is used)                     [1] */
-  int32_t coarse_cycles;/* coarse_solver 1: V-cycles per coarse solve                    [2] */
+  int32_t coarse_cycles;/* coarse_solver 1: V-cycles per coarse solve                    [1] */
+  int32_t graph_split;  /* coarse_solver 1: cube-graph levels with more nodes than this are
+                           smoothed by multi-workgroup kernels, the others (and always the
+                           smallest) inside one workgroup                           [12288] */
 } bcm_solver_opts;
 
 /* Per-call solver report (host memory). */

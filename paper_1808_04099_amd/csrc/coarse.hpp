@@ -70,6 +70,9 @@ struct CoarseMGArgs {
   const GLevel<T>* lev;     // device array of levels
   const int32_t* perm0;     // cube -> level-0 node
   int nlev;
+  int start;                // first level this workgroup solves: 0, or the first level below
+                            // the ones smoothed by the multi-workgroup kernels (its b and x
+                            // then come from and go to the levels' global buffers)
   int cycles, pre, post, bottom_iters;
   double* w;                // CG work space for the bottom level (4 * n_last doubles)
   const T* binv;            // transposed inverse of the bottom operator, or nullptr (CG)
@@ -77,5 +80,23 @@ struct CoarseMGArgs {
 };
 
 constexpr int kGraphLdsBudget = 128 * 1024;
+
+// Default of bcm_solver_opts.graph_split: graph levels with more nodes are smoothed by
+// multi-workgroup kernels (one lane per node, one launch per colour) instead of inside the
+// single workgroup.
+constexpr int kGraphSplitNodes = 12288;
+
+// Argument block of the multi-workgroup graph kernels.
+template <typename T>
+struct GStepArgs {
+  const GLevel<T>* lev;     // device array of levels (global buffers)
+  int g;                    // level
+  int lo, hi;               // node range (one colour) of a smoothing pass
+  const T* b_in;            // gather: one-cell-per-cube right-hand side (cube order)
+  T* x_out;                 // scatter: solution (cube order)
+  T* xf_out;                // and its face buffer
+  const int32_t* perm0;
+  int n_cubes;
+};
 
 }  // namespace bcm

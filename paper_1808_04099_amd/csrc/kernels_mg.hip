@@ -367,15 +367,23 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
     lv[threadIdx.x] = L;
   }
   __syncthreads();
-  const int G = a.nlev;
-  for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
-    const int i = a.perm0[c];
-    lv[0].b[i] = a.b_in[c];
-    lv[0].x[i] = T(0);
+  const int G = a.nlev, S = a.start;
+  if (S == 0) {
+    for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
+      const int i = a.perm0[c];
+      lv[0].b[i] = a.b_in[c];
+      lv[0].x[i] = T(0);
+    }
+  } else {
+    const GLevel<T>& L = a.lev[S];  // global buffers of the first level solved here
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+      if (lv[S].b != L.b) lv[S].b[i] = L.b[i];
+      lv[S].x[i] = T(0);
+    }
   }
   __syncthreads();
-  for (int cy = 0; cy < a.cycles; ++cy) {
-    for (int g = 0; g + 1 < G; ++g) {
+  for (int cy = 0; cy < (S == 0 ? a.cycles : 1); ++cy) {
+    for (int g = S; g + 1 < G; ++g) {
       g_smooth(lv[g], a.pre, true);
       g_residual(lv[g]);
       g_restrict(lv[g + 1], lv[g].r);
@@ -384,7 +392,7 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
       g_direct(lv[G - 1], a.binv);
     else
       g_bottom(lv[G - 1], a.bottom_iters, a.w, red);
-    for (int g = G - 2; g >= 0; --g) {
+    for (int g = G - 2; g >= S; --g) {
       const GLevel<T>& F = lv[g];
       const T* xc = lv[g + 1].x;
       for (int i = threadIdx.x; i < F.n; i += blockDim.x) F.x[i] += xc[F.parent[i]];
@@ -392,12 +400,94 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
       g_smooth(F, a.post, false);
     }
   }
-  for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
-    const T v = lv[0].x[a.perm0[c]];
-    a.x_out[c] = v;
+  if (S == 0) {
+    for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
+      const T v = lv[0].x[a.perm0[c]];
+      a.x_out[c] = v;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) a.xf_out[(size_t)c * face_stride(1) + f] = v;
+      for (int f = 0; f < 6; ++f) a.xf_out[(size_t)c * face_stride(1) + f] = v;
+    }
+  } else if (lv[S].x != a.lev[S].x) {
+    for (int i = threadIdx.x; i < lv[S].n; i += blockDim.x) a.lev[S].x[i] = lv[S].x[i];
   }
+}
+
+// ---- multi-workgroup kernels of the large graph levels (one lane per node) ----
+
+// Level 0 from the one-cell-per-cube right-hand side: b = b_in (permuted), x = 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_g_gather(GStepArgs<T> a) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= a.n_cubes) return;
+  const GLevel<T>& L = a.lev[0];
+  const int i = a.perm0[c];
+  L.b[i] = a.b_in[c];
+  L.x[i] = T(0);
+}
+
+// sum_w val[w][i] * x[col[w][i]] with every load of the row issued before use (W <= 16).
+template <typename T>
+__device__ __forceinline__ T g_row(const GLevel<T>& L, int i) {
+  if (L.W > 16) return g_offdiag(L, L.x, i);
+  int col[16];
+  T val[16], xv[16];
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    col[w] = w < L.W ? L.col[size_t(w) * L.n + i] : i;
+    val[w] = w < L.W ? L.val[size_t(w) * L.n + i] : T(0);
+  }
+#pragma unroll
+  for (int w = 0; w < 16; ++w) xv[w] = w < L.W ? L.x[col[w]] : T(0);
+  T acc = T(0);
+#pragma unroll
+  for (int w = 0; w < 16; ++w) acc += val[w] * xv[w];
+  return acc;
+}
+
+// One colour of a Gauss-Seidel sweep on level g: nodes [lo, hi) do not couple.
+template <typename T>
+__global__ __launch_bounds__(256) void k_g_smooth(GStepArgs<T> a) {
+  const int i = a.lo + blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.hi) return;
+  const GLevel<T>& L = a.lev[a.g];
+  L.x[i] = (L.b[i] - g_row(L, i)) / L.diag[i];
+}
+
+// Residual of level g restricted to level g+1 (volume weights), x of level g+1 set to zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_g_resid_restrict(GStepArgs<T> a) {
+  const GLevel<T>& F = a.lev[a.g];
+  const GLevel<T>& C = a.lev[a.g + 1];
+  const int J = blockIdx.x * 256 + threadIdx.x;
+  if (J >= C.n) return;
+  T acc = T(0);
+  for (int w = 0; w < C.CW; ++w) {
+    const size_t o = size_t(w) * C.n + J;
+    const int ch = C.child[o];
+    if (ch >= 0) acc += C.child_w[o] * (F.b[ch] - F.diag[ch] * F.x[ch] - g_row(F, ch));
+  }
+  C.b[J] = acc;
+  C.x[J] = T(0);
+}
+
+// x of level g += x of its parent on level g+1 (piecewise-constant prolongation).
+template <typename T>
+__global__ __launch_bounds__(256) void k_g_prolong(GStepArgs<T> a) {
+  const GLevel<T>& F = a.lev[a.g];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= F.n) return;
+  F.x[i] += a.lev[a.g + 1].x[F.parent[i]];
+}
+
+// Level-0 solution back to cube order, with its (trivial) face buffer.
+template <typename T>
+__global__ __launch_bounds__(256) void k_g_scatter(GStepArgs<T> a) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= a.n_cubes) return;
+  const T v = a.lev[0].x[a.perm0[c]];
+  a.x_out[c] = v;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) a.xf_out[(size_t)c * face_stride(1) + f] = v;
 }
 
 __global__ __launch_bounds__(256) void k_scale(ScaleArgs a) {
@@ -479,6 +569,23 @@ hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s) {
 }
 template hipError_t launch_coarse_mg<float>(const CoarseMGArgs<float>&, hipStream_t);
 template hipError_t launch_coarse_mg<double>(const CoarseMGArgs<double>&, hipStream_t);
+
+template <typename T>
+hipError_t launch_g_step(int kind, int n, const GStepArgs<T>& a, hipStream_t s) {
+  const dim3 grid((n + 255) / 256), block(256);
+  if (n <= 0) return hipSuccess;
+  switch (kind) {
+    case G_GATHER: hipLaunchKernelGGL((k_g_gather<T>), grid, block, 0, s, a); break;
+    case G_SMOOTH: hipLaunchKernelGGL((k_g_smooth<T>), grid, block, 0, s, a); break;
+    case G_RESTRICT: hipLaunchKernelGGL((k_g_resid_restrict<T>), grid, block, 0, s, a); break;
+    case G_PROLONG: hipLaunchKernelGGL((k_g_prolong<T>), grid, block, 0, s, a); break;
+    case G_SCATTER: hipLaunchKernelGGL((k_g_scatter<T>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_g_step<float>(int, int, const GStepArgs<float>&, hipStream_t);
+template hipError_t launch_g_step<double>(int, int, const GStepArgs<double>&, hipStream_t);
 
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3(a.n_cubes), dim3(WG), 0, s, a);

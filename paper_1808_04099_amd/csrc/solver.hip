@@ -88,6 +88,7 @@ struct bcm_plan {
   std::vector<GOff> g_off;
   size_t o_glev = 0, o_gw = 0, o_perm0 = 0, o_ginv = 0;
   int g_lds = 0;
+  int g_split = 0;  // leading graph levels smoothed by the multi-workgroup kernels
   Timer timer;
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
@@ -177,6 +178,52 @@ int export64(bcm_plan* P, double* x, double* xf, hipStream_t s) {
   return BCM_OK;
 }
 
+// Multigrid on the cube graph when its leading levels are large: those levels are smoothed by
+// multi-workgroup kernels (one launch per colour), the rest by the single workgroup.
+template <typename T>
+int coarse_split(bcm_plan* P, const T* b_in, T* x_out, T* xf_out, hipStream_t s) {
+  const auto& Ls = P->M->coarse.levels;
+  const int S = P->g_split, pre = 2, post = 2;
+  GStepArgs<T> ga{P->at<const GLevel<T>>(P->o_glev), 0, 0, 0, b_in, x_out, xf_out,
+                  P->at<const int32_t>(P->o_perm0), P->nc};
+  auto step = [&](int kind, int g, int n, int lo = 0, int hi = 0) -> int {
+    ga.g = g;
+    ga.lo = lo;
+    ga.hi = hi;
+    HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_g_step<T>(kind, n, ga, s); }),
+           "graph multigrid step");
+    return BCM_OK;
+  };
+  auto sweep = [&](int g, bool forward) -> int {
+    const auto& co = Ls[g].color_off;
+    const int nc = int(co.size()) - 1;
+    for (int k = 0; k < nc; ++k) {
+      const int c = forward ? k : nc - 1 - k;
+      if (int e = step(G_SMOOTH, g, co[c + 1] - co[c], co[c], co[c + 1])) return e;
+    }
+    return BCM_OK;
+  };
+  int st = step(G_GATHER, 0, P->nc);
+  for (int cy = 0; cy < P->o.coarse_cycles && !st; ++cy) {
+    for (int g = 0; g < S && !st; ++g) {
+      for (int k = 0; k < pre && !st; ++k) st = sweep(g, true);
+      if (!st) st = step(G_RESTRICT, g, Ls[g + 1].n);
+    }
+    if (st) break;
+    CoarseMGArgs<T> a{b_in, x_out, xf_out, P->at<const GLevel<T>>(P->o_glev),
+                      P->at<const int32_t>(P->o_perm0), int(P->g_off.size()), S, 1, pre, post,
+                      std::max(P->o.coarse_iters, 64), P->at<double>(P->o_gw),
+                      P->M->coarse.bottom_inv.empty() ? nullptr : P->at<const T>(P->o_ginv), P->g_lds};
+    HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse_mg<T>(a, s); }), "k_coarse_mg");
+    for (int g = S - 1; g >= 0 && !st; --g) {
+      st = step(G_PROLONG, g, Ls[g].n);
+      for (int k = 0; k < post && !st; ++k) st = sweep(g, false);
+    }
+  }
+  if (!st) st = step(G_SCATTER, 0, P->nc);
+  return st;
+}
+
 // One V-cycle on (b_0 = r, x_0 = z): per-cube levels NL = n, n/2, ..., 2 smoothed with
 // red-black Gauss-Seidel, then CG on the one-cell-per-cube level.  At level 0 the final
 // smoothing also accumulates <z, r> and (if q_dot) <z, q>.
@@ -201,9 +248,11 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
     RestrictArgs<T> ra{geom(P, NL), X(l), F(0, l), B(l), B(l + 1)};
     HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launch_restrict<T>(NL, ra, s); }), "k_restrict");
   }
-  if (P->graph) {
+  if (P->graph && P->g_split > 0) {
+    if (int st = coarse_split<T>(P, B(L - 1), X(L - 1), F(1, L - 1), s)) return st;
+  } else if (P->graph) {
     CoarseMGArgs<T> ga{B(L - 1), X(L - 1), F(1, L - 1), P->at<const GLevel<T>>(P->o_glev),
-                       P->at<const int32_t>(P->o_perm0), int(P->g_off.size()), o.coarse_cycles,
+                       P->at<const int32_t>(P->o_perm0), int(P->g_off.size()), 0, o.coarse_cycles,
                        2, 2, std::max(o.coarse_iters, 64),  // the last graph level has <= 64 nodes
                        P->at<double>(P->o_gw),
                        P->M->coarse.bottom_inv.empty() ? nullptr : P->at<const T>(P->o_ginv), P->g_lds};
@@ -602,6 +651,7 @@ void bcm_default_opts(bcm_solver_opts* o) {
   o->krylov = 1;
   o->coarse_solver = 1;
   o->coarse_cycles = 1;
+  o->graph_split = kGraphSplitNodes;
 }
 
 int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan** out,
@@ -619,7 +669,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   if (o.precision < BCM_FP64 || o.precision > BCM_MIXED_F32FIELDS || !(o.tol > 0.0) || o.max_iter < 1 ||
       o.max_outer < 1 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.pre_sweeps < 0 ||
       o.post_sweeps < 0 || o.coarse_iters < 0 || o.pre_sweeps > 16 || o.post_sweeps > 16 ||
-      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1) {
+      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1 || o.graph_split < 0) {
     set_error("bcm_plan_create: invalid solver options");
     return BCM_ERR_INVALID_ARG;
   }
@@ -694,7 +744,12 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
       go.lds_x = go.lds_b = go.lds_r = -1;
       P->g_off.push_back(go);
     }
-    // LDS placement, smallest levels first: x, then b and r, while the budget lasts
+    // levels above o.graph_split nodes are smoothed by multi-workgroup kernels (never
+    // the last one, which the single workgroup solves directly or by CG)
+    P->g_split = 0;
+    while (P->g_split + 1 < int(Ls.size()) && Ls[P->g_split].n > o.graph_split) ++P->g_split;
+    // LDS placement of the single workgroup's levels, smallest first: x, then b and r,
+    // while the budget lasts
     int lds = 0;
     auto place = [&](int& slot, size_t n) {
       const int bytes = int((n * Ti + 15) / 16 * 16);
@@ -703,8 +758,8 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
         lds += bytes;
       }
     };
-    for (int g = int(Ls.size()) - 1; g >= 0; --g) place(P->g_off[g].lds_x, Ls[g].n);
-    for (int g = int(Ls.size()) - 1; g >= 0; --g) {
+    for (int g = int(Ls.size()) - 1; g >= P->g_split; --g) place(P->g_off[g].lds_x, Ls[g].n);
+    for (int g = int(Ls.size()) - 1; g >= P->g_split; --g) {
       place(P->g_off[g].lds_b, Ls[g].n);
       place(P->g_off[g].lds_r, Ls[g].n);
     }

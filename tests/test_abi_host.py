@@ -130,6 +130,13 @@ def test_plan_workspace_and_options():
         assert sizes[2] < sizes[1] < sizes[0]
         o = L.SolverOpts()
         lib.bcm_default_opts(ctypes.byref(o))
+        assert (o.max_iter, o.max_outer, o.coarse_solver, o.coarse_cycles, o.graph_split) == \
+            (50, 10, 1, 1, 12288)
+        o.graph_split = -1
+        ph = ctypes.c_void_p()
+        nb = ctypes.c_size_t()
+        assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
+        lib.bcm_default_opts(ctypes.byref(o))
         o.tol = -1.0
         ph = ctypes.c_void_p()
         nb = ctypes.c_size_t()

@@ -85,3 +85,20 @@ def test_poisson_matches_oracle(name, precision):
     # ||e||_V <= ||r||_V / lambda_min of the V-symmetric operator; checked loosely via the
     # residual and directly against the exact solve
     assert rel_err(p, ref) <= 1e-7
+
+
+@pytest.mark.parametrize("name", ["channel_n4", "multilevel_small_n4", "tiny_3level_n2"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_split_graph_multigrid_matches_oracle(name, precision):
+    """graph_split = 0 smooths every cube-graph level but the last with the multi-workgroup
+    kernels (the path large multi-level meshes take by default)."""
+    m = _meshes()[name]
+    log(f"split graph {name} {precision}")
+    fv = FVMesh(m)
+    b = np.random.default_rng(19).standard_normal(m.n_cells)
+    p, rep = plan_for(m, precision, graph_split=0).poisson_solve(dev(b))
+    p = host(p)
+    rr = fv.residual_norm(p, b)
+    log(f"  iters={rep.n_inner} outer={rep.n_outer} oracle={rr:.3e}")
+    assert rep.status == 0 and rr <= 1.2e-10
+    assert rel_err(p, fv.solve(b)) <= 1e-7
