@@ -206,6 +206,7 @@ __device__ __forceinline__ void zero_tail(double* part, int units) {
 template <typename T, int NL, bool POST, bool ML>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 && !ML) ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
+  constexpr bool PF = sizeof(T) == 4 || NL < 16;
   __shared__ T tile[C::CPB * C::TS];
   __shared__ double red[8];
   const int t = threadIdx.x;
@@ -238,10 +239,11 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && !ML) ? 3 : 1) void kc_smoot
   };
   int u = blockIdx.x;
   int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
-  if (u < U) fetch(c < 0 ? 0 : c);
+  if (PF && u < U) fetch(c < 0 ? 0 : c);
   double zr = 0.0, zq = 0.0;
   while (u < U) {
     const int ce = c < 0 ? 0 : c;
+    if (!PF) fetch(ce);  // FP64 at 16^3: no prefetch (registers go to occupancy)
     T x[NL], bv[NL];
     T zlo = T(0), zhi = T(0);
     const CubeMeta& m = a.g.meta[ce];
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && !ML) ? 3 : 1) void kc_smoot
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
     __syncthreads();
-    if (un < U) fetch(cn < 0 ? 0 : cn);
+    if (PF && un < U) fetch(cn < 0 ? 0 : cn);
     // q of this cube for the fused <x, q> (loads overlap the sweeps)
     T q[NL];
     if (dots && a.q_dot) {
@@ -327,6 +329,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && !ML) ? 3 : 1) void kc_smoot
 template <typename T, int NL, bool ML>
 __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
   using C = Col<NL>;
+  constexpr bool PF = sizeof(T) == 4 || NL < 16;
   __shared__ T tile[C::CPB * C::TS];
   __shared__ T rsum[C::CPB * C::H * C::N2];  // residual summed over k pairs, per (slot, kk, j, i)
   const int t = threadIdx.x;
@@ -352,9 +355,10 @@ __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
   };
   int u = blockIdx.x;
   int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
-  if (u < U) fetch(c < 0 ? 0 : c);
+  if (PF && u < U) fetch(c < 0 ? 0 : c);
   while (u < U) {
     const int ce = c < 0 ? 0 : c;
+    if (!PF) fetch(ce);  // FP64 at 16^3: no prefetch (registers go to occupancy)
     T x[NL], bv[NL], hv[6];
     T zlo, zhi;
     const CubeMeta& m = a.g.meta[ce];
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
     __syncthreads();
-    if (un < U) fetch(cn < 0 ? 0 : cn);
+    if (PF && un < U) fetch(cn < 0 ? 0 : cn);
 #pragma unroll
     for (int kk = 0; kk < C::H; ++kk) {
       T acc = T(0);
@@ -407,6 +411,7 @@ __global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
 template <typename T, int NL, bool ML>
 __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   using C = Col<NL>;
+  constexpr bool PF = sizeof(T) == 4 || NL < 16;
   __shared__ T tile[C::CPB * C::TS];
   __shared__ double red[8];
   const int t = threadIdx.x;
@@ -434,10 +439,11 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   };
   int u = blockIdx.x;
   int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
-  if (u < U) fetch(c < 0 ? 0 : c);
+  if (PF && u < U) fetch(c < 0 ? 0 : c);
   double pq = 0.0;
   while (u < U) {
     const int ce = c < 0 ? 0 : c;
+    if (!PF) fetch(ce);  // FP64 at 16^3: no prefetch (registers go to occupancy)
     T x[NL], hv[6];
     T zlo, zhi;
     const CubeMeta& m = a.g.meta[ce];
@@ -457,7 +463,7 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
     __syncthreads();
-    if (un < U) fetch(cn < 0 ? 0 : cn);
+    if (PF && un < U) fetch(cn < 0 ? 0 : cn);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const T d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
