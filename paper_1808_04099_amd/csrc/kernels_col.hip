@@ -204,7 +204,7 @@ __device__ __forceinline__ void zero_tail(double* part, int units) {
 // red-black order from a zero initial guess.
 // ------------------------------------------------------------------------------------------
 template <typename T, int NL, bool POST, bool ML>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && !ML) ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
   __shared__ T tile[C::CPB * C::TS];

@@ -171,7 +171,7 @@ int n_wg(int NL, int nc) {
   return (nc + c - 1) / c;
 }
 
-// Export the faces of an FP64 field (k_ir without an update).
+// Export the faces of an FP64 field (kc_ir without an update).
 int export64(bcm_plan* P, double* x, double* xf, hipStream_t s) {
   IrArgs<float> a{geom(P, P->n), x, nullptr, xf, 0.0};
   HIPCHK(timed(P, cls_of("export", 0), s, [&] { return launch_ir<float>(P->n, a, s); }), "export faces");
@@ -244,9 +244,9 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
     sa.sweeps = o.pre_sweeps;
     sa.black_first = 0;
     sa.zero_init = 1;
-    HIPCHK(timed(P, cls_of("presmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "k_smooth (pre)");
+    HIPCHK(timed(P, cls_of("presmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "kc_smooth (pre)");
     RestrictArgs<T> ra{geom(P, NL), X(l), F(0, l), B(l), B(l + 1)};
-    HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launch_restrict<T>(NL, ra, s); }), "k_restrict");
+    HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launch_restrict<T>(NL, ra, s); }), "kc_restrict");
   }
   if (P->graph && P->g_split > 0) {
     if (int st = coarse_split<T>(P, B(L - 1), X(L - 1), F(1, L - 1), s)) return st;
@@ -281,7 +281,7 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
       sa.part_zr = P->at<double>(P->o_part[0]);
       sa.part_zq = q_dot ? P->at<double>(P->o_part[1]) : nullptr;
     }
-    HIPCHK(timed(P, cls_of("postsmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "k_smooth (post)");
+    HIPCHK(timed(P, cls_of("postsmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "kc_smooth (post)");
   }
   return BCM_OK;
 }
@@ -315,7 +315,7 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     ApplyArgs<T> aa{geom(P, NL), z, P->at<T>(P->o_zf[1]), p, P->at<T>(P->o_pfk[P->pf_cur]),
                     P->at<T>(P->o_pfk[P->pf_cur ^ 1]), q, P->at<const Scalars>(P->o_sc),
                     (!fcg || it == 0) ? 1 : 0, P->at<double>(P->o_part[2])};
-    HIPCHK(timed(P, cls_of("apply", NL), s, [&] { return launch_apply<T>(NL, aa, s); }), "k_apply");
+    HIPCHK(timed(P, cls_of("apply", NL), s, [&] { return launch_apply<T>(NL, aa, s); }), "kc_apply");
     P->pf_cur ^= 1;
     if ((st = finalize(P, OP_PQ, 2, -1, nparts, 0, s))) return st;
     if (!fcg) {  // stationary iteration: x += z, r -= A z  (alpha = 1)
@@ -349,7 +349,7 @@ int residual64(bcm_plan* P, const double* p, const double* b, TO* r, double rsca
   }
   Resid64Args<TO> ra{geom(P, NL), p, P->at<const double>(P->o_pf), b, r,
                      P->at<double>(P->o_part[0]), P->at<double>(P->o_part[1]), rscale};
-  HIPCHK(timed(P, cls_of("resid64", 0), s, [&] { return launch_resid64<TO>(NL, ra, s); }), "k_resid64");
+  HIPCHK(timed(P, cls_of("resid64", 0), s, [&] { return launch_resid64<TO>(NL, ra, s); }), "kc_resid64");
   return finalize(P, OP_BB, 0, 1, partials_of(NL, P->nc), 0, s);
 }
 
@@ -437,8 +437,8 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
       if ((st = krylov<float>(P, d, true, thr, o.max_iter, 1.0 / (rscale * std::sqrt(bb)), log, &hs, s)))
         return st;
       IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale};
-      HIPCHK(timed(P, cls_of("ir", 0), s, [&] { return launch_ir<float>(P->n, ia, s); }), "k_ir");
-      faces_ok = true;  // k_ir exports the faces of the updated p
+      HIPCHK(timed(P, cls_of("ir", 0), s, [&] { return launch_ir<float>(P->n, ia, s); }), "kc_ir");
+      faces_ok = true;  // kc_ir exports the faces of the updated p
       const double rr_est = hs.rr / (rscale * rscale);
       if (rr_est > 0 && std::isfinite(rr_est)) rscale = 1.0 / std::sqrt(rr_est / vol);
     }
@@ -869,7 +869,7 @@ int bcm_apply_laplacian(bcm_plan* P, const double* d_p, double* d_Ap, void* stre
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = export64(P, const_cast<double*>(d_p), P->at<double>(P->o_pf), s))) return st;
   Resid64Args<double> ra{geom(P, P->n), d_p, P->at<const double>(P->o_pf), nullptr, d_Ap, nullptr, nullptr, 1.0};
-  HIPCHK(timed(P, cls_of("resid64", 0), s, [&] { return launch_resid64<double>(P->n, ra, s); }), "k_resid64 (apply)");
+  HIPCHK(timed(P, cls_of("resid64", 0), s, [&] { return launch_resid64<double>(P->n, ra, s); }), "kc_resid64 (apply)");
   return BCM_OK;
 }
 
