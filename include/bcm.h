@@ -5,10 +5,11 @@
  * (Sec. 3: immersed-body forcing, pressure Poisson equation, velocity correction) on a
  * building-cube mesh (Sec. 2.2: cubes of equal cell count n^3, 2:1 size ratio between
  * face neighbours, a neighbour adjacency table instead of a tree).  The Poisson equation
- * is solved by geometric multigrid coarsened inside each cube, with a conjugate-gradient
- * solve on the one-cell-per-cube level (Sec. 3 and Sec. 7: at most 10 coarse CG
- * iterations, at most 50 V-cycles), here wrapped in flexible CG and, in the mixed modes,
- * in FP64 iterative refinement.
+ * is solved by geometric multigrid coarsened inside each cube (Sec. 3), here wrapped in
+ * flexible CG and, in the mixed modes, in FP64 iterative refinement.  On the
+ * one-cell-per-cube level the paper runs a conjugate-gradient solve (Sec. 7: at most 10
+ * iterations, at most 50 V-cycles); by default this library runs multigrid on the cube graph
+ * there instead (coarse_solver), with the paper's CG kept as an option.
  *
  * Conventions shared by every call:
  *   - All field pointers are DEVICE pointers owned by the caller.  Scalar fields are
@@ -106,7 +107,8 @@ typedef struct {
   int32_t pre_sweeps;   /* red-black Gauss-Seidel sweeps before restriction             [2] */
   int32_t post_sweeps;  /* sweeps after prolongation                                    [2] */
   int32_t coarse_iters; /* CG iterations on the one-cell-per-cube level (coarse_solver 0),
-                           or on the smallest cube-graph level (coarse_solver 1)       [10] */
+                           or on the smallest cube-graph level when it is not solved
+                           directly (coarse_solver 1; at least 64 are used there)      [10] */
   int32_t krylov;       /* 1 = flexible CG preconditioned by one V-cycle, 0 = V-cycles  [1] */
   int32_t coarse_solver;/* one-cell-per-cube level: 0 = CG only (the paper's scheme),
                            1 = multigrid on the cube graph (octree, then lattice merging;

@@ -10,10 +10,17 @@
 // The solver kernels are persistent: a workgroup walks units of CPB cubes with stride
 // gridDim.x (a multiple of 8, so each workgroup stays on the XCD that owns its stretch of the
 // Z-ordered launch table) and, while it computes one unit, the loads of its next unit are in
-// flight.  The prefetch does integer work only: the halo addresses are computed branch-free
-// from the face relations and the loads land in raw registers that are combined when the cube
-// is staged, because any arithmetic on a loaded value makes the in-order load counter wait
-// for every load issued before it (the prefetched columns included).
+// flight (except FP64 at 16^3, where the registers are worth more as occupancy).  The
+// prefetch does integer work only: the halo addresses are computed branch-free from the face
+// relations and the loads land in raw registers that are combined when the cube is staged,
+// because any arithmetic on a loaded value makes the in-order load counter wait for every
+// load issued before it (the prefetched columns included).
+//
+// Whole-field values are read and written with non-temporal hints (each is touched once per
+// launch); face slabs, metadata and scalars use ordinary cached accesses.
+//
+// Multi-level meshes (2:1 faces) use the ML variants: one halo value per face cell still, the
+// finer side exporting 2x2 means of the faces that border a coarser cube (face_stride).
 #include <algorithm>
 
 #include "kernels.hpp"

@@ -1,7 +1,8 @@
 // Host orchestration of the projection path: workspace plan, multigrid V-cycle coarsened
-// inside each cube with a conjugate-gradient solve on the one-cell-per-cube level (Sec. 3,
-// Sec. 7), flexible CG wrapper, FP64 iterative refinement of FP32 inner solves, projection
-// step (Sec. 3) and its adjoint, exposed through the C ABI of bcm.h.
+// inside each cube down to one cell per cube (Sec. 3), where multigrid on the cube graph (or
+// the paper's conjugate-gradient solve, Sec. 7) takes over, flexible CG wrapper, FP64
+// iterative refinement of FP32 inner solves, projection step (Sec. 3) and its adjoint,
+// exposed through the C ABI of bcm.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -225,8 +226,9 @@ int coarse_split(bcm_plan* P, const T* b_in, T* x_out, T* xf_out, hipStream_t s)
 }
 
 // One V-cycle on (b_0 = r, x_0 = z): per-cube levels NL = n, n/2, ..., 2 smoothed with
-// red-black Gauss-Seidel, then CG on the one-cell-per-cube level.  At level 0 the final
-// smoothing also accumulates <z, r> and (if q_dot) <z, q>.
+// red-black Gauss-Seidel, then the one-cell-per-cube level (cube-graph multigrid, or the
+// paper's CG with coarse_solver 0).  At level 0 the final smoothing also accumulates <z, r>
+// and (if q_dot) <z, q>.
 template <typename T>
 int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
   const int L = P->nlev;
