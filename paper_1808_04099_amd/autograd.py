@@ -3,11 +3,11 @@
 Projection           one step (u~, alpha, U_in) -> (u^{n+1}, p); backward calls the hand-written
                      adjoint kernels (transposed correction, transposed Poisson solve, transposed
                      face interpolation / divergence / forcing) through bcm_project_adjoint.
-MultiStepProjection  K steps u^{k+1} = P(F(u^k)) with per-step pressure checkpoints (each solve warm-started from the previous
-                     step's pressure): forward keeps
-                     u^0 and p^0..p^{K-1} only; backward recomputes each u^k from u^0 with
-                     bcm_project_recompute (forcing + correction, no solve) and runs the adjoint
-                     steps in reverse.
+MultiStepProjection  K steps u^{k+1} = P(F(u^k)) with per-step pressure checkpoints (each
+                     solve warm-started from the previous step's pressure): forward keeps u^0
+                     and p^0..p^{K-1} only; backward recomputes each u^k from u^0 with
+                     bcm_project_recompute (forcing + correction, no solve) and runs the
+                     adjoint steps in reverse.
 """
 from __future__ import annotations
 
