@@ -1,4 +1,6 @@
-// LDS tile machinery shared by the stencil kernels (device code).
+// LDS tile machinery of the projection and adjoint kernels for every cube size and of the
+// face export (device code), plus the operator rules and reductions that the column kernels
+// of the solver (kernels_col.hip) share.
 //
 // A workgroup owns CPB cubes of NL^3 cells at one multigrid level.  Each cube is staged in
 // LDS as an (NL+2)^3 tile: the cube's cells plus a one-cell halo on its six faces (no edges
@@ -6,8 +8,9 @@
 // buffers of the neighbouring cubes: every field with a halo carries a buffer
 // faces[cube][face][t2][t1] of the cube's own boundary layer (t1, t2 = tangential cell
 // indices, first tangential axis fastest), written by the kernel that produced the field.
-// The halo fill reads those contiguous 1-D slabs instead of strided columns of the
-// neighbour's cube, and applies the face relation:
+// (Behind the six slabs the buffer holds their 2x2 means, see face_stride; the tile kernels
+// do not use them.)  The halo fill reads those contiguous 1-D slabs instead of strided
+// columns of the neighbour's cube, and applies the face relation:
 //   same level    -> the neighbour's boundary cell;
 //   coarser (2:1) -> the coarse cell covering this fine cell's face quadrant;
 //   finer (2:1)   -> the mean of the 2x2 fine cells covering this cell's face;
@@ -202,22 +205,6 @@ __device__ __forceinline__ void fill_halo(T* tile, const CubeMeta* sm, const int
   }
 }
 
-// Write the boundary layer of each staged cube into its face buffer.
-template <int NL, typename T, typename TO>
-__device__ __forceinline__ void export_faces(TO* faces, const T* tile, const int* cube) {
-  constexpr int CPB = Lv<NL>::CPB, N2 = Lv<NL>::N2, TILE = Lv<NL>::TILE;
-  for (int e = threadIdx.x; e < CPB * 6 * N2; e += blockDim.x) {
-    const int s = e / (6 * N2);
-    const int r = e - s * 6 * N2;
-    const int f = r / N2;
-    const int t = r - f * N2;
-    if (cube[s] < 0) continue;
-    int i, j, k;
-    face_cell<NL>(f, t % NL, t / NL, i, j, k);
-    faces[(size_t)cube[s] * Lv<NL>::FACE + r] = TO(tile[s * TILE + ti<NL>(i, j, k)]);
-  }
-}
-
 // Deterministic workgroup sum (fixed shuffle tree, then waves in order); valid on thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
@@ -244,33 +231,5 @@ template <typename T>
 struct BcZero {
   __device__ T operator()(const CubeMeta&, int) const { return T(0); }
 };
-
-// (sum of the six neighbour terms, sum of the six own coefficients) of cell (i,j,k) under RULE_P.
-template <int NL, typename T>
-__device__ __forceinline__ void stencil_p(const T* t, const CubeMeta& m, int i, int j, int k,
-                                          T& nb, T& dg) {
-  const int c = ti<NL>(i, j, k);
-  constexpr int T1 = NL + 2, T2 = (NL + 2) * (NL + 2);
-  nb = t[c - 1] + t[c + 1] + t[c - T1] + t[c + T1] + t[c - T2] + t[c + T2];
-  T d = T(6);
-  if (i == 0) d += T(RuleTab<RULE_P>::own(m.kind[0])) - T(1);
-  if (i == NL - 1) d += T(RuleTab<RULE_P>::own(m.kind[1])) - T(1);
-  if (j == 0) d += T(RuleTab<RULE_P>::own(m.kind[2])) - T(1);
-  if (j == NL - 1) d += T(RuleTab<RULE_P>::own(m.kind[3])) - T(1);
-  if (k == 0) d += T(RuleTab<RULE_P>::own(m.kind[4])) - T(1);
-  if (k == NL - 1) d += T(RuleTab<RULE_P>::own(m.kind[5])) - T(1);
-  dg = d;
-}
-
-template <int NL, typename T>
-__device__ __forceinline__ void zero_halo(T* tile, const int* cube) {
-  constexpr int CPB = Lv<NL>::CPB, N2 = Lv<NL>::N2, TILE = Lv<NL>::TILE;
-  for (int e = threadIdx.x; e < CPB * 6 * N2; e += blockDim.x) {
-    const int s = e / (6 * N2);
-    const int r = e - s * 6 * N2;
-    const int f = r / N2, t = r - f * N2;
-    tile[s * TILE + halo_idx<NL>(f, t % NL, t / NL)] = T(0);
-  }
-}
 
 }  // namespace bcm
