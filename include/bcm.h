@@ -116,7 +116,8 @@ typedef struct {
   int32_t coarse_cycles;/* coarse_solver 1: V-cycles per coarse solve                    [1] */
   int32_t graph_split;  /* coarse_solver 1: cube-graph levels with more nodes than this are
                            smoothed by multi-workgroup kernels, the others (and always the
-                           smallest) inside one workgroup                           [12288] */
+                           smallest) inside one workgroup; -1 = automatic: the leading
+                           levels whose x, b and r do not fit in the workgroup's LDS  [-1] */
 } bcm_solver_opts;
 
 /* Per-call solver report (host memory). */

@@ -81,11 +81,6 @@ struct CoarseMGArgs {
 
 constexpr int kGraphLdsBudget = 128 * 1024;
 
-// Default of bcm_solver_opts.graph_split: graph levels with more nodes are smoothed by
-// multi-workgroup kernels (one lane per node, one launch per colour) instead of inside the
-// single workgroup.
-constexpr int kGraphSplitNodes = 12288;
-
 // Argument block of the multi-workgroup graph kernels.
 template <typename T>
 struct GStepArgs {

@@ -653,7 +653,7 @@ void bcm_default_opts(bcm_solver_opts* o) {
   o->krylov = 1;
   o->coarse_solver = 1;
   o->coarse_cycles = 1;
-  o->graph_split = kGraphSplitNodes;
+  o->graph_split = -1;
 }
 
 int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan** out,
@@ -671,7 +671,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   if (o.precision < BCM_FP64 || o.precision > BCM_MIXED_F32FIELDS || !(o.tol > 0.0) || o.max_iter < 1 ||
       o.max_outer < 1 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.pre_sweeps < 0 ||
       o.post_sweeps < 0 || o.coarse_iters < 0 || o.pre_sweeps > 16 || o.post_sweeps > 16 ||
-      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1 || o.graph_split < 0) {
+      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1 || o.graph_split < -1) {
     set_error("bcm_plan_create: invalid solver options");
     return BCM_ERR_INVALID_ARG;
   }
@@ -746,10 +746,15 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
       go.lds_x = go.lds_b = go.lds_r = -1;
       P->g_off.push_back(go);
     }
-    // levels above o.graph_split nodes are smoothed by multi-workgroup kernels (never
-    // the last one, which the single workgroup solves directly or by CG)
+    // leading levels above o.graph_split nodes (automatic: those whose x, b and r do not fit
+    // in the LDS budget) are smoothed by multi-workgroup kernels; never the last one, which
+    // the single workgroup solves directly or by CG
+    auto large = [&](int g) {
+      return o.graph_split >= 0 ? Ls[g].n > o.graph_split
+                                : size_t(3) * Ls[g].n * Ti > size_t(kGraphLdsBudget);
+    };
     P->g_split = 0;
-    while (P->g_split + 1 < int(Ls.size()) && Ls[P->g_split].n > o.graph_split) ++P->g_split;
+    while (P->g_split + 1 < int(Ls.size()) && large(P->g_split)) ++P->g_split;
     // LDS placement of the single workgroup's levels, smallest first: x, then b and r,
     // while the budget lasts
     int lds = 0;

@@ -131,8 +131,8 @@ def test_plan_workspace_and_options():
         o = L.SolverOpts()
         lib.bcm_default_opts(ctypes.byref(o))
         assert (o.max_iter, o.max_outer, o.coarse_solver, o.coarse_cycles, o.graph_split) == \
-            (50, 10, 1, 1, 12288)
-        o.graph_split = -1
+            (50, 10, 1, 1, -1)
+        o.graph_split = -2
         ph = ctypes.c_void_p()
         nb = ctypes.c_size_t()
         assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
