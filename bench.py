@@ -207,15 +207,19 @@ def run(args):
     for _ in range(args.warmup):
         rep = step(plan, u, a, out)
     torch.cuda.synchronize()
-    # time each kernel class over one untimed step (one class timed per step); the dominant
+    # time each kernel class over two untimed steps (one class timed per step); the dominant
     # one is the class with the largest share of the step
     dominant, best = args.kernel, -1.0
     class_ms = {}
     for cls in () if args.kernel else ("presmooth16", "postsmooth16", "restrict16", "apply16",
                                        "update", "resid64", "ir", "coarse", "force", "div",
                                        "correct"):
-        _, _, (nl, tot) = timed_steps(plan, u, a, out, 1, cls)
+        _, _, (nl, tot) = timed_steps(plan, u, a, out, 2, cls)
+        nl, tot = nl // 2, tot / 2.0       # per step
         class_ms[cls] = {"launches": nl, "ms_per_step": tot}
+        if cls != "coarse" and nl > 0:
+            gbs = alg_bytes_per_cell(cls, s, f) * n_cells / (tot / nl * 1e-3) / 1e9
+            class_ms[cls].update(alg_gbs=gbs, frac=gbs / PEAK_HBM_GBS)
         log(f"[bench] {cls}: {nl} launches, {tot:.3f} ms per step")
         if args.kernel is None and cls != "coarse" and tot > best:
             dominant, best = cls, tot
