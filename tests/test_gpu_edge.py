@@ -111,3 +111,36 @@ def test_alpha_one_sets_the_body_velocity_before_projection():
     unew = np.stack([host(x) for x in out["u_new"]])
     assert np.abs(unew[0] - 0.7).max() <= 1e-12 and np.abs(unew[1:]).max() <= 1e-12
     assert np.abs(host(out["p"])).max() <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_results_are_bitwise_reproducible(precision):
+    """Every reduction sums its partials in a fixed order, so repeated calls agree exactly."""
+    m = uniform_mesh((4, 2, 2), 0.25, 16, CHANNEL_BC)
+    u = uniform_random_velocity(m, 9, 0.3, (1.0, 0.0, 0.0))
+    alpha = np.random.default_rng(9).uniform(0.0, 1.0, m.n_cells)
+    plan = plan_for(m, precision)
+    args = ([dev(u[d]) for d in range(3)], dev(alpha), 1.0, 0.01, 1.0)
+    a = plan.project(*args)
+    b = plan.project(*args)
+    assert a["report"].n_inner == b["report"].n_inner
+    assert a["report"].history == b["report"].history
+    assert np.array_equal(host(a["p"]), host(b["p"]))
+    for d in range(3):
+        assert np.array_equal(host(a["u_new"][d]), host(b["u_new"][d]))
+
+
+def test_runs_on_the_callers_stream():
+    """All work is enqueued on the stream current at the call (a non-default torch stream)."""
+    m = uniform_mesh((2, 2, 2), 0.5, 16, CHANNEL_BC)
+    u = uniform_random_velocity(m, 10, 0.3, (1.0, 0.0, 0.0))
+    plan = plan_for(m, "mixed")
+    ref = plan.project([dev(u[d]) for d in range(3)], None, 1.0, 0.01, 1.0)
+    ref_p = host(ref["p"])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        uu = [dev(u[d]) for d in range(3)]
+        out = plan.project(uu, None, 1.0, 0.01, 1.0)
+        p = out["p"].to("cpu", torch.float64)  # ordered after the projection on stream s
+    s.synchronize()
+    assert np.array_equal(p.numpy(), ref_p)
