@@ -102,3 +102,23 @@ def test_split_graph_multigrid_matches_oracle(name, precision):
     log(f"  iters={rep.n_inner} outer={rep.n_outer} oracle={rr:.3e}")
     assert rep.status == 0 and rr <= 1.2e-10
     assert rel_err(p, fv.solve(b)) <= 1e-7
+
+
+@pytest.mark.parametrize("name", ["channel_n16", "multilevel_small_n4"])
+@pytest.mark.parametrize("opts", [dict(coarse_solver=0, max_iter=200), dict(krylov=0, max_iter=200),
+                                  dict(coarse_cycles=2), dict(pre_sweeps=1, post_sweeps=3)],
+                         ids=["paper_cg", "vcycle_iteration", "two_graph_cycles", "sweeps_1_3"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solver_variants_match_oracle(name, opts, precision):
+    """The paper's scheme (CG capped at coarse_iters on the one-cell-per-cube level, plain
+    V-cycle iteration) and other option settings reach the same solution."""
+    m = _meshes()[name]
+    log(f"variant {name} {opts} {precision}")
+    fv = FVMesh(m)
+    b = np.random.default_rng(23).standard_normal(m.n_cells)
+    p, rep = plan_for(m, precision, **opts).poisson_solve(dev(b))
+    p = host(p)
+    rr = fv.residual_norm(p, b)
+    log(f"  iters={rep.n_inner} outer={rep.n_outer} oracle={rr:.3e}")
+    assert rep.status == 0 and rr <= 1.2e-10
+    assert rel_err(p, fv.solve(b)) <= 1e-7
