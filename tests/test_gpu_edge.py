@@ -144,3 +144,25 @@ def test_runs_on_the_callers_stream():
         p = out["p"].to("cpu", torch.float64)  # ordered after the projection on stream s
     s.synchronize()
     assert np.array_equal(p.numpy(), ref_p)
+
+
+def test_workspace_binding_is_checked():
+    """bcm_plan_bind refuses a workspace smaller than reported or not 256-byte aligned."""
+    import ctypes
+    from paper_1808_04099_amd import _lib as L
+    from paper_1808_04099_amd.api import Mesh
+    lib = L.load()
+    mesh = Mesh(uniform_mesh((2, 1, 1), 0.5, 8, CHANNEL_BC))
+    o = L.SolverOpts()
+    lib.bcm_default_opts(ctypes.byref(o))
+    ph, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    assert lib.bcm_plan_create(mesh.handle, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == 0
+    try:
+        ws = torch.empty(nb.value + 512, dtype=torch.uint8, device="cuda")
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        base = ws.data_ptr()
+        assert lib.bcm_plan_bind(ph, ctypes.c_void_p(base), nb.value - 256, stream) == -3
+        assert lib.bcm_plan_bind(ph, ctypes.c_void_p(base + 8), nb.value, stream) == -3
+        assert lib.bcm_plan_bind(ph, ctypes.c_void_p(base), nb.value, stream) == 0
+    finally:
+        lib.bcm_plan_destroy(ph)
