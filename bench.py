@@ -262,6 +262,9 @@ def run(args):
         "kernel_classes": class_ms,
     }
     if args.compare_fp64 and prec != "fp64":
+        # keep this precision's result of the last timed step to compare with the FP64 one
+        p_mixed = out["p"].clone()
+        u_mixed = [x.to(torch.float64) for x in out["u_new"]]
         del plan, out
         torch.cuda.empty_cache()
         p64, u64, a64, o64 = make("fp64")
@@ -272,6 +275,14 @@ def run(args):
         result["fp64_iterations"] = reps64[-1].n_inner
         result["fp64_final_rel_res"] = reps64[-1].final_rel_res
         result["mixed_speedup_vs_fp64"] = ms64 / ms
+        # max-norm difference of this precision's result from the all-FP64 one, relative to
+        # the largest value (both solves reach the same 1e-10 residual)
+        rel = lambda a, b: float((a - b).abs().max() / b.abs().max())
+        result["rel_diff_vs_fp64"] = {
+            "p": rel(p_mixed, o64["p"]),
+            "u_new": max(rel(u_mixed[d], o64["u_new"][d]) for d in range(3))}
+        log(f"[bench] difference from the FP64 result: p {result['rel_diff_vs_fp64']['p']:.1e}, "
+            f"u {result['rel_diff_vs_fp64']['u_new']:.1e}")
         log(f"[bench] fp64: {ms64:.2f} ms/step, {reps64[-1].n_inner} its; "
             f"mixed speed-up {ms64 / ms:.2f}x")
         del p64, o64
