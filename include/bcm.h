@@ -118,6 +118,9 @@ typedef struct {
                            smoothed by multi-workgroup kernels, the others (and always the
                            smallest) inside one workgroup; -1 = automatic: the leading
                            levels whose x, b and r do not fit in the workgroup's LDS  [-1] */
+  int32_t prolong;      /* per-cube multigrid prolongation: 1 = trilinear over the cube's
+                           27-neighbourhood (single-level meshes; meshes with 2:1 faces use
+                           0), 0 = piecewise constant                                   [1] */
 } bcm_solver_opts;
 
 /* Per-call solver report (host memory). */

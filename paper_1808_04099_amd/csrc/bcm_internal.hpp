@@ -42,11 +42,23 @@ struct HostMesh {
   std::vector<int8_t> face_bc;    // [n_cubes][6]
   std::vector<CubeMeta> meta;     // derived device metadata
   std::vector<int32_t> launch;    // workgroup -> cube (Z-ordered, XCD-aware)
+  std::vector<uint32_t> nb27;     // [launch position][27] resolved neighbours (pack_nb27);
+                                  // single-level meshes only, else empty
   int max_level = 0;
   bool multilevel = false;
   bool has_inflow = false;
   CoarseHierarchy coarse;         // multigrid levels of the one-cell-per-cube graph
 };
+
+// One entry of the 27-neighbourhood table: the cube that holds the cell at offset
+// (dx, dy, dz) in {-1, 0, 1}^3 from a cube, reached by stepping along x, then y, then z; a step
+// across a domain boundary stays in the cube and marks that axis as clamped (the ghost mirrors
+// the boundary cell), negated once per open (p = 0) face crossed.
+//   bits 0..23: cube index; bits 24..26: clamped axes x, y, z; bit 27: negate.
+constexpr uint32_t pack_nb27(int cube, int clamped, bool negate) {
+  return uint32_t(cube) | (uint32_t(clamped) << 24) | (uint32_t(negate) << 27);
+}
+constexpr int kNb27MaxCubes = 1 << 24;
 
 void set_error(const std::string& msg);
 

@@ -35,6 +35,8 @@ struct SmoothArgs {
   T* xf_out;            // faces of x after the launch
   const T* xc;          // coarse correction to add first (level NL/2) or nullptr
   const T* xcf;         // its faces
+  const uint32_t* nb27; // per launch position, the 27-neighbourhood of the cube: trilinear
+                        // prolongation of xc (single-level meshes); nullptr = piecewise constant
   int sweeps, black_first, zero_init;
   const T* r_dot;       // fused <x, r_dot>_V and <x, q_dot>_V (level 0 of a Krylov step)
   const T* q_dot;

@@ -206,15 +206,201 @@ __device__ __forceinline__ void zero_tail(double* part, int units) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Trilinear prolongation on single-level meshes.  Each cube slot of the workgroup gets a
+// padded tile of the next coarser level: its (NL/2)^3 cells plus one layer on every side
+// (faces, edges and corners), taken from the cube's 27-neighbourhood (pack_nb27), so that a
+// fine cell next to a cube face interpolates from the neighbouring cube's coarse cells just as
+// it would inside one cube.  Along each axis a fine cell takes 3/4 of the coarse cell that
+// holds it and 1/4 of the next coarse cell on its side.  The fine halo of the post-smoother
+// is the neighbour's own value after its prolongation: the neighbour's face cell interpolates
+// from coarse cells that all lie in this padded tile, so it is computed here the same way.
+// ------------------------------------------------------------------------------------------
+template <int NL>
+struct Pro {
+  static constexpr int H = NL / 2, W = H + 2, P3 = W * W * W;
+  // padded coordinates 0..H+1 (0 and H+1 are the neighbours' layers)
+  __device__ static int ix(int s, int I, int J, int K) { return s * P3 + (K * W + J) * W + I; }
+  // padded coarse index of fine index f (0..NL-1) and of the coarse cell on its side
+  __device__ static int own(int f) { return (f >> 1) + 1; }
+  __device__ static int side(int f) { return (f >> 1) + 1 + ((f & 1) ? 1 : -1); }
+};
+
+// Coordinate in the source cube of a padded coordinate P along one axis, given the step taken
+// (d: 0 = none, -1 / +1) and whether the step was clamped at a domain boundary.
+template <int H>
+__device__ __forceinline__ int nb_coord(int P, int d, bool clamped) {
+  if (d == 0) return P - 1;
+  if (d < 0) return clamped ? 0 : H - 1;
+  return clamped ? H - 1 : 0;
+}
+
+// Fill the padded coarse tiles of unit u from the coarse field xc.
+template <int NL, typename T>
+__device__ __forceinline__ void fill_coarse(T* ct, const T* xc, const uint32_t* nb27, int n_cubes,
+                                            int u) {
+  using C = Col<NL>;
+  using Q = Pro<NL>;
+  for (int e = threadIdx.x; e < C::CPB * Q::P3; e += 256) {
+    const int s2 = e / Q::P3, r = e - s2 * Q::P3;
+    const int I = r % Q::W, J = (r / Q::W) % Q::W, K = r / (Q::W * Q::W);
+    const int p = C::CPB == 1 ? u : ((u >> 3) * C::CPB + s2) * 8 + (u & 7);
+    T v = T(0);
+    if (p < n_cubes) {
+      const int dx = I == 0 ? -1 : (I == Q::W - 1 ? 1 : 0);
+      const int dy = J == 0 ? -1 : (J == Q::W - 1 ? 1 : 0);
+      const int dz = K == 0 ? -1 : (K == Q::W - 1 ? 1 : 0);
+      const uint32_t ent = nb27[(size_t)p * 27 + ((dz + 1) * 3 + (dy + 1)) * 3 + (dx + 1)];
+      const int id = int(ent & 0xFFFFFFu), cl = int(ent >> 24) & 7;
+      const int I2 = nb_coord<Q::H>(I, dx, cl & 1), J2 = nb_coord<Q::H>(J, dy, cl & 2),
+                K2 = nb_coord<Q::H>(K, dz, cl & 4);
+      v = xc[(size_t)id * C::H3 + (K2 * Q::H + J2) * Q::H + I2];
+      if (ent & (1u << 27)) v = -v;
+    }
+    ct[e] = v;
+  }
+}
+
+// Prefetched form of fill_coarse.  The 27 table entries of each cube slot of a unit go to
+// LDS (one load per lane, issued one unit ahead), the tile elements of a unit are spread over
+// the lanes, NE per lane, and their values land in raw registers that are signed when they
+// are written to LDS: no load waits on a load issued in the same step.
+template <int NL>
+struct ProPF {
+  static constexpr int NT = Col<NL>::CPB * Pro<NL>::P3;  // tile elements per unit
+  static constexpr int NE = (NT + 255) / 256;             // per lane
+  static constexpr int NN = Col<NL>::CPB * 27;            // table entries per unit
+  static constexpr int NEE = (NN + 255) / 256;            // per lane
+};
+
+template <int NL>
+__device__ __forceinline__ void coarse_ent(const uint32_t* nb27, int n_cubes, int u,
+                                           uint32_t (&ent)[ProPF<NL>::NEE]) {
+  using C = Col<NL>;
+#pragma unroll
+  for (int m = 0; m < ProPF<NL>::NEE; ++m) {
+    const int d = threadIdx.x + 256 * m, s2 = d / 27;
+    const int p = C::CPB == 1 ? u : ((u >> 3) * C::CPB + s2) * 8 + (u & 7);
+    const bool ok = d < ProPF<NL>::NN && p < n_cubes;
+    ent[m] = ok ? nb27[(size_t)(ok ? p : 0) * 27 + (d - s2 * 27)] : ~0u;
+  }
+}
+
+template <int NL>
+__device__ __forceinline__ void coarse_ent_put(uint32_t* cent, const uint32_t (&ent)[ProPF<NL>::NEE]) {
+#pragma unroll
+  for (int m = 0; m < ProPF<NL>::NEE; ++m) {
+    const int d = threadIdx.x + 256 * m;
+    if (d < ProPF<NL>::NN) cent[d] = ent[m];
+  }
+}
+
+// Unit-independent description of tile element e: bits 0..9 its source offset within the
+// source cube when no step is clamped, bits 10..14 its direction (0..26), bits 15..20 its
+// cube slot.  Computed once per workgroup.
+template <int NL>
+__device__ __forceinline__ uint32_t coarse_desc(int e) {
+  using Q = Pro<NL>;
+  const int s2 = e / Q::P3, r = e - s2 * Q::P3;
+  const int I = r % Q::W, J = (r / Q::W) % Q::W, K = r / (Q::W * Q::W);
+  const int dx = I == 0 ? -1 : (I == Q::W - 1 ? 1 : 0);
+  const int dy = J == 0 ? -1 : (J == Q::W - 1 ? 1 : 0);
+  const int dz = K == 0 ? -1 : (K == Q::W - 1 ? 1 : 0);
+  const int off = (nb_coord<Q::H>(K, dz, false) * Q::H + nb_coord<Q::H>(J, dy, false)) * Q::H +
+                  nb_coord<Q::H>(I, dx, false);
+  const int dir = ((dz + 1) * 3 + (dy + 1)) * 3 + (dx + 1);
+  return uint32_t(off) | (uint32_t(dir) << 10) | (uint32_t(s2) << 15);
+}
+
+// Issue the value loads of one unit from its entries in LDS; sg gets bit m = negate, bit
+// 16 + m = element present.  A clamped step moves the source coordinate from the far layer
+// of the neighbour to the near layer of the cube itself: d (H - 1) cells along that axis.
+template <int NL, typename T>
+__device__ __forceinline__ void coarse_val(const T* xc, const uint32_t* cdesc, const uint32_t* cent,
+                                           T (&cv)[ProPF<NL>::NE], uint32_t& sg) {
+  using C = Col<NL>;
+  using Q = Pro<NL>;
+  sg = 0;
+#pragma unroll
+  for (int m = 0; m < ProPF<NL>::NE; ++m) {
+    const int e = threadIdx.x + 256 * m;
+    const bool in = e < ProPF<NL>::NT;
+    const uint32_t ds = cdesc[in ? e : 0];
+    const int dir = int(ds >> 10) & 31;
+    const uint32_t en = in ? cent[int(ds >> 15) * 27 + dir] : ~0u;
+    const bool ok = en != ~0u;
+    const int cl = int(en >> 24) & 7;
+    const int dx = dir % 3 - 1, dy = (dir / 3) % 3 - 1, dz = dir / 9 - 1;
+    const int off = int(ds & 1023u) + ((cl & 1) ? dx * (Q::H - 1) : 0) +
+                    ((cl & 2) ? dy * (Q::H - 1) * Q::H : 0) + ((cl & 4) ? dz * (Q::H - 1) * Q::H * Q::H : 0);
+    const int id = ok ? int(en & 0xFFFFFFu) : 0;
+    cv[m] = xc[(size_t)id * C::H3 + (ok ? off : 0)];
+    sg |= (ok ? (1u << (16 + m)) : 0u) | ((ok && (en >> 27 & 1u)) ? (1u << m) : 0u);
+  }
+}
+
+template <int NL, typename T>
+__device__ __forceinline__ void coarse_put(T* ct, const T (&cv)[ProPF<NL>::NE], uint32_t sg) {
+#pragma unroll
+  for (int m = 0; m < ProPF<NL>::NE; ++m) {
+    const int e = threadIdx.x + 256 * m;
+    if (e < ProPF<NL>::NT) {
+      const T v = (sg >> m & 1u) ? -cv[m] : cv[m];
+      ct[e] = (sg >> (16 + m) & 1u) ? v : T(0);
+    }
+  }
+}
+
+// Trilinear value from the padded tile: (a0, a1), (b0, b1), (c0, c1) are the near and far
+// coarse cells along x, y and z.
+template <int NL, typename T>
+__device__ __forceinline__ T tri8(const T* ct, int s, int a0, int a1, int b0, int b1, int c0, int c1) {
+  using Q = Pro<NL>;
+  auto row = [&](int b, int c) { return T(0.75) * ct[Q::ix(s, a0, b, c)] + T(0.25) * ct[Q::ix(s, a1, b, c)]; };
+  const T v0 = T(0.75) * row(b0, c0) + T(0.25) * row(b1, c0);
+  const T v1 = T(0.75) * row(b0, c1) + T(0.25) * row(b1, c1);
+  return T(0.75) * v0 + T(0.25) * v1;
+}
+
+// Prolongated correction of the lane's column (e[k]) and of its six halo cells (eh[f]): the
+// x/y halos at tangential (t1, t2) = (i, j) as the stage() ring expects, the z halos of the
+// column.
+template <int NL, typename T>
+__device__ __forceinline__ void tri_column(const T* ct, const LaneC<NL>& L, T (&e)[NL], T (&eh)[6]) {
+  using Q = Pro<NL>;
+  const int s = L.s, i = L.i, j = L.j;
+  const int a0 = Q::own(i), a1 = Q::side(i), b0 = Q::own(j), b1 = Q::side(j);
+  T v[Q::W];
+#pragma unroll
+  for (int K = 0; K < Q::W; ++K) {
+    const T r0 = T(0.75) * ct[Q::ix(s, a0, b0, K)] + T(0.25) * ct[Q::ix(s, a1, b0, K)];
+    const T r1 = T(0.75) * ct[Q::ix(s, a0, b1, K)] + T(0.25) * ct[Q::ix(s, a1, b1, K)];
+    v[K] = T(0.75) * r0 + T(0.25) * r1;
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) e[k] = T(0.75) * v[Q::own(k)] + T(0.25) * v[Q::side(k)];
+  eh[4] = T(0.75) * v[0] + T(0.25) * v[1];
+  eh[5] = T(0.75) * v[Q::W - 1] + T(0.25) * v[Q::W - 2];
+  // x faces: (y, z) = (i, j); y faces: (x, z) = (i, j)
+  eh[0] = tri8<NL, T>(ct, s, 0, 1, a0, a1, b0, b1);
+  eh[1] = tri8<NL, T>(ct, s, Q::W - 1, Q::W - 2, a0, a1, b0, b1);
+  eh[2] = tri8<NL, T>(ct, s, a0, a1, 0, 1, b0, b1);
+  eh[3] = tri8<NL, T>(ct, s, a0, a1, Q::W - 1, Q::W - 2, b0, b1);
+}
+
+// ------------------------------------------------------------------------------------------
 // Smoother (red-black Gauss-Seidel): POST = prolongation of the coarse correction + smoothing
 // in black-red order (+ fused <x, b> and <x, q> on the finest level), else smoothing in
-// red-black order from a zero initial guess.
+// red-black order from a zero initial guess.  TRI: trilinear prolongation (single-level
+// meshes), else piecewise constant.
 // ------------------------------------------------------------------------------------------
-template <typename T, int NL, bool POST, bool ML>
+template <typename T, int NL, bool POST, bool ML, bool TRI = false>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
   __shared__ T tile[C::CPB * C::TS];
+  __shared__ T ctile[TRI ? C::CPB * Pro<NL>::P3 : 1];
+  __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
+  __shared__ uint32_t cdesc[TRI && PF ? ProPF<NL>::NT : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
   const LaneC<NL> L(t);
@@ -231,21 +417,36 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
       if (POST) nx[k] = ld_nt(a.x + g);
     }
     if (POST) {
+      if (!TRI) {
 #pragma unroll
-      for (int kk = 0; kk < C::H; ++kk)
-        nxc[kk] = a.xc[(size_t)cc * C::H3 + (kk * C::H + (j >> 1)) * C::H + (i >> 1)];
+        for (int kk = 0; kk < C::H; ++kk)
+          nxc[kk] = a.xc[(size_t)cc * C::H3 + (kk * C::H + (j >> 1)) * C::H + (i >> 1)];
+      }
       Slots S;
       slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
         kinds[f] = S.kind[f];
         rf[f] = a.xf_in[S.fine[f]];
-        rc[f] = a.xcf[S.coarse[f]];
+        if (!TRI) rc[f] = a.xcf[S.coarse[f]];
       }
     }
   };
+  // trilinear prolongation with prefetch: entries one unit ahead of the values
+  uint32_t entn[ProPF<NL>::NEE];
+  T cvn[ProPF<NL>::NE];
+  uint32_t sgn = 0;
   int u = blockIdx.x;
   int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
+  if (TRI && PF && u < U) {
+    for (int e = t; e < ProPF<NL>::NT; e += 256) cdesc[e] = coarse_desc<NL>(e);
+    coarse_ent<NL>(a.nb27, a.g.n_cubes, u, entn);
+    coarse_ent_put<NL>(cent, entn);
+    __syncthreads();
+    coarse_val<NL, T>(a.xc, cdesc, cent, cvn, sgn);
+    __syncthreads();
+    if (u + G < U) coarse_ent<NL>(a.nb27, a.g.n_cubes, u + G, entn);
+  }
   if (PF && u < U) fetch(c < 0 ? 0 : c);
   double zr = 0.0, zq = 0.0;
   while (u < U) {
@@ -254,16 +455,29 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
     T x[NL], bv[NL];
     T zlo = T(0), zhi = T(0);
     const CubeMeta& m = a.g.meta[ce];
+    T eh[6];
+    if (TRI) {
+      if (PF) {
+        coarse_put<NL, T>(ctile, cvn, sgn);
+        if (u + G < U) coarse_ent_put<NL>(cent, entn);  // entries of the next unit
+      } else
+        fill_coarse<NL, T>(ctile, a.xc, a.nb27, a.g.n_cubes, u);
+      __syncthreads();
+      T e[NL];
+      tri_column<NL, T>(ctile, L, e, eh);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) x[k] = nx[k] + e[k];
+    }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-      x[k] = POST ? nx[k] + nxc[k >> 1] : T(0);
+      if (!TRI) x[k] = POST ? nx[k] + nxc[k >> 1] : T(0);
       bv[k] = nb[k];
       tile[C::tix(L.s, i, j, k)] = x[k];
     }
     if (POST) {
       T hv[6];
 #pragma unroll
-      for (int f = 0; f < 6; ++f) hv[f] = halo_val<T>(kinds[f], rf[f] + rc[f]);
+      for (int f = 0; f < 6; ++f) hv[f] = halo_val<T>(kinds[f], rf[f] + (TRI ? eh[f] : rc[f]));
       stage<NL, T>(tile, hv, L, zlo, zhi);
     } else {
 #pragma unroll
@@ -278,7 +492,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
     __syncthreads();
-    if (PF && un < U) fetch(cn < 0 ? 0 : cn);
+    if (PF && un < U) {
+      if (TRI) {
+        coarse_val<NL, T>(a.xc, cdesc, cent, cvn, sgn);
+        if (un + G < U) coarse_ent<NL>(a.nb27, a.g.n_cubes, un + G, entn);
+      }
+      fetch(cn < 0 ? 0 : cn);
+    }
     // q of this cube for the fused <x, q> (loads overlap the sweeps)
     T q[NL];
     if (dots && a.q_dot) {
@@ -836,6 +1056,7 @@ hipError_t launchc_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s) {
       return launch_col(kc_smooth<T, NLC, true, true>, cpb, a, s);
     }
     if (a.zero_init) return launch_col(kc_smooth<T, NLC, false, false>, cpb, a, s);
+    if (a.nb27) return launch_col(kc_smooth<T, NLC, true, false, true>, cpb, a, s);
     return launch_col(kc_smooth<T, NLC, true, false>, cpb, a, s);
   });
   return hipSuccess;

@@ -194,6 +194,29 @@ void derive(HostMesh& M) {
       const int p = x * chunk + i;
       if (p < nc) M.launch.push_back(order[p]);
     }
+  // 27-neighbourhoods for the trilinear prolongation (single-level meshes)
+  M.nb27.clear();
+  if (!M.multilevel && nc < kNb27MaxCubes) {
+    M.nb27.resize(size_t(nc) * 27);
+    for (int p = 0; p < nc; ++p)
+      for (int e = 0; e < 27; ++e) {
+        const int d[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
+        int c = M.launch[p], clamped = 0;
+        bool neg = false;
+        for (int a = 0; a < 3; ++a) {
+          if (d[a] == 0) continue;
+          const int f = 2 * a + (d[a] > 0);
+          const CubeMeta& m = M.meta[c];
+          if (m.kind[f] == FK_SAME) {
+            c = m.nbr[f][0];
+          } else {
+            clamped |= 1 << a;
+            neg ^= m.kind[f] == FK_OUTFLOW;
+          }
+        }
+        M.nb27[size_t(p) * 27 + e] = pack_nb27(c, clamped, neg);
+      }
+  }
   build_coarse_hierarchy(M, M.coarse, kMaxGraphLevels);
   for (const CoarseLevel& L : M.coarse.levels)
     if (int(L.color_off.size()) - 1 > 8) M.coarse.ok = false;  // device keeps 8 colours

@@ -75,6 +75,7 @@ struct bcm_plan {
   char* ws = nullptr;
   // workspace offsets
   size_t o_meta = 0, o_launch = 0, o_part[3] = {0, 0, 0}, o_sc = 0, o_cw = 0;
+  size_t o_nb27 = 0;  // 27-neighbourhoods (trilinear prolongation), 0 = not used
   size_t o_ustar[3] = {0, 0, 0}, o_uf = 0, o_b64 = 0, o_pf = 0, o_lam = 0;
   size_t o_r = 0, o_z = 0, o_p = 0, o_q = 0, o_d = 0;
   size_t o_zf[2] = {0, 0}, o_pfk[2] = {0, 0};
@@ -274,6 +275,7 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
     sa.xf_out = F(1, l);
     sa.xc = X(l + 1);
     sa.xcf = F(1, l + 1);
+    sa.nb27 = P->o_nb27 ? P->at<const uint32_t>(P->o_nb27) : nullptr;
     sa.sweeps = o.post_sweeps;
     sa.black_first = 1;
     sa.zero_init = 0;
@@ -654,6 +656,7 @@ void bcm_default_opts(bcm_solver_opts* o) {
   o->coarse_solver = 1;
   o->coarse_cycles = 1;
   o->graph_split = -1;
+  o->prolong = 1;
 }
 
 int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan** out,
@@ -671,7 +674,8 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   if (o.precision < BCM_FP64 || o.precision > BCM_MIXED_F32FIELDS || !(o.tol > 0.0) || o.max_iter < 1 ||
       o.max_outer < 1 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.pre_sweeps < 0 ||
       o.post_sweeps < 0 || o.coarse_iters < 0 || o.pre_sweeps > 16 || o.post_sweeps > 16 ||
-      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1 || o.graph_split < -1) {
+      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1 || o.graph_split < -1 ||
+      o.prolong < 0 || o.prolong > 1) {
     set_error("bcm_plan_create: invalid solver options");
     return BCM_ERR_INVALID_ARG;
   }
@@ -695,6 +699,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   size_t top = 0;
   P->o_meta = take(top, nc * sizeof(CubeMeta));
   P->o_launch = take(top, nc * sizeof(int32_t));
+  if (o.prolong == 1 && !M.nb27.empty()) P->o_nb27 = take(top, M.nb27.size() * sizeof(uint32_t));
   const size_t nparts = std::max(nc, size_t(partials_of(P->n, int(nc))));
   for (int i = 0; i < 3; ++i) P->o_part[i] = take(top, nparts * sizeof(double));
   P->o_sc = take(top, sizeof(Scalars));
@@ -804,6 +809,9 @@ int bcm_plan_bind(bcm_plan* P, void* d_ws, size_t bytes, void* stream) {
                         hipMemcpyHostToDevice, s), "upload cube metadata");
   HIPCHK(hipMemcpyAsync(P->ws + P->o_launch, M.launch.data(), M.launch.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice, s), "upload launch order");
+  if (P->o_nb27)
+    HIPCHK(hipMemcpyAsync(P->ws + P->o_nb27, M.nb27.data(), M.nb27.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, s), "upload 27-neighbourhoods");
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   if (P->graph) return P->inner32 ? upload_graph<float>(P, s) : upload_graph<double>(P, s);
   return BCM_OK;

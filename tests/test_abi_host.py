@@ -130,11 +130,14 @@ def test_plan_workspace_and_options():
         assert sizes[2] < sizes[1] < sizes[0]
         o = L.SolverOpts()
         lib.bcm_default_opts(ctypes.byref(o))
-        assert (o.max_iter, o.max_outer, o.coarse_solver, o.coarse_cycles, o.graph_split) == \
-            (50, 10, 1, 1, -1)
+        assert (o.max_iter, o.max_outer, o.coarse_solver, o.coarse_cycles, o.graph_split,
+                o.prolong) == (50, 10, 1, 1, -1, 1)
         o.graph_split = -2
         ph = ctypes.c_void_p()
         nb = ctypes.c_size_t()
+        assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
+        lib.bcm_default_opts(ctypes.byref(o))
+        o.prolong = 2
         assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
         lib.bcm_default_opts(ctypes.byref(o))
         o.tol = -1.0

@@ -106,8 +106,10 @@ def test_split_graph_multigrid_matches_oracle(name, precision):
 
 @pytest.mark.parametrize("name", ["channel_n16", "multilevel_small_n4"])
 @pytest.mark.parametrize("opts", [dict(coarse_solver=0, max_iter=200), dict(krylov=0, max_iter=200),
-                                  dict(coarse_cycles=2), dict(pre_sweeps=1, post_sweeps=3)],
-                         ids=["paper_cg", "vcycle_iteration", "two_graph_cycles", "sweeps_1_3"])
+                                  dict(coarse_cycles=2), dict(pre_sweeps=1, post_sweeps=3),
+                                  dict(prolong=0)],
+                         ids=["paper_cg", "vcycle_iteration", "two_graph_cycles", "sweeps_1_3",
+                              "constant_prolongation"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solver_variants_match_oracle(name, opts, precision):
     """The paper's scheme (CG capped at coarse_iters on the one-cell-per-cube level, plain
@@ -122,3 +124,19 @@ def test_solver_variants_match_oracle(name, opts, precision):
     log(f"  iters={rep.n_inner} outer={rep.n_outer} oracle={rr:.3e}")
     assert rep.status == 0 and rr <= 1.2e-10
     assert rel_err(p, fv.solve(b)) <= 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_trilinear_prolongation_needs_fewer_iterations(precision):
+    """On a single-level channel of 16^3 cubes the trilinear prolongation (default) reaches the
+    tolerance in fewer Krylov iterations than the piecewise-constant one, at the same solution."""
+    m = uniform_mesh((8, 4, 4), 0.125, 16, CHANNEL_BC)
+    b = np.random.default_rng(31).standard_normal(m.n_cells)
+    its, sols = {}, {}
+    for pro in (0, 1):
+        p, rep = plan_for(m, precision, prolong=pro).poisson_solve(dev(b))
+        assert rep.status == 0
+        its[pro], sols[pro] = rep.n_inner, host(p)
+    log(f"trilinear {its[1]} vs constant {its[0]} iterations ({precision})")
+    assert its[1] < its[0]
+    assert rel_err(sols[1], sols[0]) <= 1e-6
