@@ -392,11 +392,24 @@ __device__ __forceinline__ void tri_column(const T* ct, const LaneC<NL>& L, T (&
 // in black-red order (+ fused <x, b> and <x, q> on the finest level), else smoothing in
 // red-black order from a zero initial guess.  TRI: trilinear prolongation (single-level
 // meshes), else piecewise constant.
+//
+// The sweeps keep the column x (b in bv) in registers, the x/y neighbours in the LDS tile and
+// the z halo in zlo / zhi, with one barrier per colour.  In a column the colour of cell k
+// alternates, in phase with the lane's (i + j) parity; three forms of the same update order
+// differ in how a lane reaches its cells of one colour:
+//   masked:  every k, with the lanes of the other colour idle;
+//   paired:  one cell of each pair (2n, 2n + 1), picked per lane by selects;
+//   shifted: the column is copied into slots shifted by the parity (slot s = k + par + 1, the
+//            z halo in slots par and NL + par + 1), so that one colour sits in the same slots
+//            on every lane.
 // ------------------------------------------------------------------------------------------
 template <typename T, int NL, bool POST, bool ML, bool TRI = false>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
+  // sweep form (same update order): shifted columns before restriction; with the trilinear
+  // prolongation the paired form in FP32 (fewer registers), else the masked form
+  constexpr int SWEEP = !POST ? 2 : (TRI && sizeof(T) == 4 ? 1 : 0);
   __shared__ T tile[C::CPB * C::TS];
   __shared__ T ctile[TRI ? C::CPB * Pro<NL>::P3 : 1];
   __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
@@ -505,11 +518,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
 #pragma unroll
       for (int k = 0; k < NL; ++k) q[k] = ld_nt(a.q_dot + (size_t)ce * C::N3 + k * C::N2 + L.l);
     }
+    if constexpr (SWEEP == 0) {
     for (int sw = 0; sw < a.sweeps; ++sw) {
-#pragma unroll
+  #pragma unroll
       for (int col = 0; col < 2; ++col) {
-        const int colour = POST ? (col ^ 1) : col;  // pre: red first, post: black first
-#pragma unroll
+        const int colour = POST ? (col ^ 1) : col;
+  #pragma unroll
         for (int k = 0; k < NL; ++k) {
           if (((i + j + k) & 1) != colour) continue;
           const int cc = C::tix(L.s, i, j, k);
@@ -520,6 +534,70 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
         }
         __syncthreads();
       }
+    }
+    } else if constexpr (SWEEP == 1) {
+    const int par = (i + j) & 1;
+    for (int sw = 0; sw < a.sweeps; ++sw) {
+  #pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        const int colour = POST ? (col ^ 1) : col;
+        const bool odd = (colour ^ par) != 0;  // this lane updates k = 2n + 1, else k = 2n
+  #pragma unroll
+        for (int n = 0; n < NL / 2; ++n) {
+          const int k0 = 2 * n, k1 = 2 * n + 1;
+          const int cc = C::tix(L.s, i, j, k0) + (odd ? C::P : 0);
+          const T zm = odd ? x[k0] : (k0 > 0 ? x[k0 > 0 ? k0 - 1 : 0] : zlo);
+          const T zp = odd ? (k1 < NL - 1 ? x[k1 < NL - 1 ? k1 + 1 : 0] : zhi) : x[k1];
+          const T sum = tile[cc - 1] + tile[cc + 1] + tile[cc - C::W] + tile[cc + C::W] + zm + zp;
+          const T id = odd ? (k1 == NL - 1 ? il : im) : (k0 == 0 ? i0 : im);
+          const T xn = (sum - h2 * (odd ? bv[k1] : bv[k0])) * id;
+          x[k0] = odd ? x[k0] : xn;
+          x[k1] = odd ? xn : x[k1];
+          tile[cc] = xn;
+        }
+        __syncthreads();
+      }
+    }
+    } else {
+    const int par = (i + j) & 1;
+    auto col_at = [&](int k) { return k == -1 ? zlo : (k == NL ? zhi : (k >= 0 && k < NL ? x[k >= 0 && k < NL ? k : 0] : T(0))); };
+    auto b_at = [&](int k) { return k >= 0 && k < NL ? bv[k >= 0 && k < NL ? k : 0] : T(0); };
+    T y[NL + 3], yb[NL + 3];
+  #pragma unroll
+    for (int sl = 0; sl < NL + 3; ++sl) {
+      y[sl] = par ? col_at(sl - 2) : col_at(sl - 1);
+      yb[sl] = par ? b_at(sl - 2) : b_at(sl - 1);
+    }
+    const int tb = C::tix(L.s, i, j, 0) - (1 + par) * C::P;  // LDS index of slot s: tb + s P
+    for (int sw = 0; sw < a.sweeps; ++sw) {
+  #pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        const int colour = POST ? (col ^ 1) : col;
+  #pragma unroll
+        for (int sl = 1; sl <= NL + 1; ++sl) {
+          if ((sl & 1) != (colour ^ 1)) continue;  // the colour's slots (the same on every lane)
+          // slot 1 is a cell only on par = 0 lanes, slot NL + 1 only on par = 1 lanes
+          const bool valid = sl == 1 ? par == 0 : (sl == NL + 1 ? par == 1 : true);
+          const int cc = tb + sl * C::P;
+          const T sum = tile[valid ? cc - 1 : 0] + tile[valid ? cc + 1 : 0] +
+                        tile[valid ? cc - C::W : 0] + tile[valid ? cc + C::W : 0] + y[sl - 1] + y[sl + 1];
+          // k = sl - 1 - par: the first cell sits at slot 1 or 2, the last at NL or NL + 1
+          const T id = sl == 1 ? i0 : (sl == 2 ? (par ? i0 : im)
+                                               : (sl == NL ? (par ? im : il) : (sl == NL + 1 ? il : im)));
+          const T xn = (sum - h2 * yb[sl]) * id;
+          if (sl == 1 || sl == NL + 1) {
+            y[sl] = valid ? xn : y[sl];
+            if (valid) tile[cc] = xn;
+          } else {
+            y[sl] = xn;
+            tile[cc] = xn;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  #pragma unroll
+    for (int k = 0; k < NL; ++k) x[k] = par ? y[k + 2] : y[k + 1];
     }
     if (c >= 0) {
 #pragma unroll
