@@ -30,9 +30,9 @@ PEAK_HBM_GBS = 8000.0
 # timer class, for inner precision size s (4 for mixed, 8 for fp64) and field size f.
 def alg_bytes_per_cell(cls, s, f):
     return {
-        "presmooth16": 2 * s,            # read b, write x (zero initial guess)
+        "presmooth16": 2 * s + s / 8,    # read b; write x and the restricted residual
         "postsmooth16": 4 * s + s / 8,   # read x, b, q, coarse correction; write x
-        "restrict16": 2 * s + s / 8,     # read x, b; write restricted residual
+        "restrict16": s / 4,             # the restricted residual's cross-cube terms: read, write
         "apply16": 4 * s,                # read z, p; write p, q
         "update": 6 * s,                 # read x, p, r, q; write x, r
         "resid64": 16 + s,               # read p, b (FP64); write r

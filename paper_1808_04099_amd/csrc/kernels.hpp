@@ -38,6 +38,8 @@ struct SmoothArgs {
   const uint32_t* nb27; // per launch position, the 27-neighbourhood of the cube: trilinear
                         // prolongation of xc (single-level meshes); nullptr = piecewise constant
   int sweeps, black_first, zero_init;
+  T* bc;                // pre-smoother: restricted residual with the cross-cube terms left out
+                        // (completed by the face correction), or nullptr
   const T* r_dot;       // fused <x, r_dot>_V and <x, q_dot>_V (level 0 of a Krylov step)
   const T* q_dot;
   double* part_zr;
@@ -45,12 +47,10 @@ struct SmoothArgs {
 };
 
 template <typename T>
-struct RestrictArgs {
+struct RestrictFixArgs {
   Geom g;
-  const T* x;
-  const T* xf;
-  const T* b;
-  T* bc;                // restricted residual, level NL/2
+  const T* xf;          // faces of the pre-smoothed iterate
+  T* bc;                // restricted residual, level NL/2 (in/out)
 };
 
 template <typename T>
@@ -201,7 +201,6 @@ struct ScaleArgs {      // y = x * (vol ^ power) per cube (power = +1 or -1)
 
 // Launchers (return hipError_t of the launch).
 template <typename T> hipError_t launch_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s);
-template <typename T> hipError_t launch_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_apply(int NL, const ApplyArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_update(const UpdateArgs<T>& a, hipStream_t s);
 template <typename TO> hipError_t launch_resid64(int NL, const Resid64Args<TO>& a, hipStream_t s);
@@ -230,7 +229,7 @@ __host__ __device__ inline int col_units(int cpb, int n_cubes) {
   return cpb == 1 ? n_cubes : 8 * ((n_cubes + 8 * cpb - 1) / (8 * cpb));
 }
 template <typename T> hipError_t launchc_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s);
-template <typename T> hipError_t launchc_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launchc_rfix(int NL, const RestrictFixArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launchc_apply(int NL, const ApplyArgs<T>& a, hipStream_t s);
 template <typename TO> hipError_t launchc_resid64(int NL, const Resid64Args<TO>& a, hipStream_t s);
 template <typename T> hipError_t launchc_ir(int NL, const IrArgs<T>& a, hipStream_t s);

@@ -414,6 +414,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
   __shared__ T ctile[TRI ? C::CPB * Pro<NL>::P3 : 1];
   __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
   __shared__ uint32_t cdesc[TRI && PF ? ProPF<NL>::NT : 1];
+  __shared__ T rsum[POST ? 1 : C::CPB * C::H * C::N2];  // pre: residual summed over k pairs
   __shared__ double red[8];
   const int t = threadIdx.x;
   const LaneC<NL> L(t);
@@ -611,6 +612,32 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
       export_col<NL, T>(a.xf_out, c, x, i, j);
       if (ML) export_avg<NL, T>(a.xf_out, c, tile, m, L);
     }
+    if (!POST && a.bc) {
+      // residual with the halo the sweeps used (zero across cube faces), summed over the 2x2x2
+      // children of each coarse cell; the face correction adds the cross-cube terms
+      const T ih2 = T(1) / h2;
+#pragma unroll
+      for (int kk = 0; kk < C::H; ++kk) {
+        T acc = T(0);
+#pragma unroll
+        for (int q2 = 0; q2 < 2; ++q2) {
+          const int k = 2 * kk + q2;
+          const T d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
+          const T sum = nbsum<NL, T>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
+          acc += bv[k] - (sum - d * x[k]) * ih2;
+        }
+        rsum[(L.s * C::H + kk) * C::N2 + L.l] = acc;
+      }
+      __syncthreads();
+      for (int e = t; e < C::CPB * C::H3; e += 256) {
+        const int s2 = e / C::H3, le = e - s2 * C::H3;
+        const int I = le % C::H, J = (le / C::H) % C::H, K = le / C::H2;
+        const int base = (s2 * C::H + K) * C::N2 + 2 * J * NL + 2 * I;
+        const T sum = rsum[base] + rsum[base + 1] + rsum[base + NL] + rsum[base + NL + 1];
+        const int c2 = unit_cube<NL>(a.g, u, s2);
+        if (c2 >= 0) a.bc[(size_t)c2 * C::H3 + le] = sum * T(0.125);
+      }
+    }
     if (ML) __syncthreads();  // the means read the tile the next cube overwrites
     u = un;
     c = cn;
@@ -630,85 +657,82 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
   }
 }
 
-// Residual of x and restriction to the next level (mean of the 8 children).
+// Completes the restriction fused into the pre-smoother.  A coarse cell on a cube's boundary
+// still lacks the cross-cube terms of its children's residuals, -(1/8) sum nbeff x_nb / h^2
+// over the children's faces that border a neighbour.  Lane (i, j) of each cube slot gathers
+// the six halo values at tangential (t1, t2) = (i, j) (as the smoothers do), the 2x2 children
+// of each coarse face cell are summed in LDS, and each coarse boundary cell adds the sums of
+// its faces in the order x, y, z.
 template <typename T, int NL, bool ML>
-__global__ __launch_bounds__(256) void kc_restrict(RestrictArgs<T> a) {
+__global__ __launch_bounds__(256) void kc_rfix(RestrictFixArgs<T> a) {
   using C = Col<NL>;
-  constexpr bool PF = sizeof(T) == 4 || NL < 16;
-  __shared__ T tile[C::CPB * C::TS];
-  __shared__ T rsum[C::CPB * C::H * C::N2];  // residual summed over k pairs, per (slot, kk, j, i)
-  const int t = threadIdx.x;
-  const LaneC<NL> L(t);
-  const int i = L.i, j = L.j;
+  constexpr int NE = (C::CPB * C::H3 + 255) / 256;  // coarse cells per lane
+  __shared__ T hv[C::CPB * 6 * C::N2];
+  const LaneC<NL> L(threadIdx.x);
   const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
-  T nx[NL], nb[NL], rf[6];
-  int kinds[6];
-  auto fetch = [&](int cc) {
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
-      nx[k] = ld_nt(a.x + g);
-      nb[k] = ld_nt(a.b + g);
-    }
+  // per unit: the lane's six raw halo values and its coarse cells' current values, loaded one
+  // unit ahead (raw registers, combined after the loads of the next unit are issued)
+  T rf[6], bv[NE];
+  int kinds[6], faces[NE];  // faces: bit f = the cell lies on face f of a cube present
+  size_t at_g[NE];
+  auto fetch = [&](int uu) {
+    const int c = unit_cube<NL>(a.g, uu, L.s);
     Slots S;
-    slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
+    slots<NL, ML>(a.g.meta[c < 0 ? 0 : c], c < 0 ? 0 : c, L.i, L.j, S);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-      kinds[f] = S.kind[f];
+      kinds[f] = c < 0 ? FK_OUTFLOW : S.kind[f];
       rf[f] = a.xf[S.fine[f]];
+    }
+#pragma unroll
+    for (int n = 0; n < NE; ++n) {
+      const int e = threadIdx.x + 256 * n;
+      const int s2 = e / C::H3, le = e - s2 * C::H3;
+      const int I = le % C::H, J = (le / C::H) % C::H, K = le / C::H2;
+      const int c2 = e < C::CPB * C::H3 ? unit_cube<NL>(a.g, uu, s2) : -1;
+      faces[n] = c2 < 0 ? 0
+                        : (I == 0) | (I == C::H - 1) << 1 | (J == 0) << 2 | (J == C::H - 1) << 3 |
+                              (K == 0) << 4 | (K == C::H - 1) << 5;
+      at_g[n] = (size_t)(c2 < 0 ? 0 : c2) * C::H3 + le;
+      bv[n] = a.bc[at_g[n]];
     }
   };
   int u = blockIdx.x;
-  int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
-  if (PF && u < U) fetch(c < 0 ? 0 : c);
+  if (u < U) fetch(u);
   while (u < U) {
-    const int ce = c < 0 ? 0 : c;
-    if (!PF) fetch(ce);  // FP64 at 16^3: no prefetch (registers go to occupancy)
-    T x[NL], bv[NL], hv[6];
-    T zlo, zhi;
-    const CubeMeta& m = a.g.meta[ce];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      x[k] = nx[k];
-      bv[k] = nb[k];
-      tile[C::tix(L.s, i, j, k)] = x[k];
-    }
+    for (int f = 0; f < 6; ++f) hv[(L.s * 6 + f) * C::N2 + L.l] = halo_val<T>(kinds[f], rf[f]);
+    T cb[NE];
+    int cf[NE];
+    size_t cg[NE];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) hv[f] = halo_val<T>(kinds[f], rf[f]);
-    stage<NL, T>(tile, hv, L, zlo, zhi);
-    const T h = T(m.h * a.g.hscale);
-    const T ih2 = T(1) / (h * h);
-    T d0, dm, dl;
-    diag<NL, T>(m, i, j, d0, dm, dl);
-    const int un = u + G;
-    const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
-    __syncthreads();
-    if (PF && un < U) fetch(cn < 0 ? 0 : cn);
-#pragma unroll
-    for (int kk = 0; kk < C::H; ++kk) {
-      T acc = T(0);
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int k = 2 * kk + q;
-        const T d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
-        const T sum = nbsum<NL, T>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
-        acc += bv[k] - (sum - d * x[k]) * ih2;
-      }
-      rsum[(L.s * C::H + kk) * C::N2 + L.l] = acc;
+    for (int n = 0; n < NE; ++n) {
+      cb[n] = bv[n];
+      cf[n] = faces[n];
+      cg[n] = at_g[n];
     }
     __syncthreads();
-    // coarse cells of the unit: sum the 2x2 (i, j) neighbours of each k-pair sum
-    for (int e = t; e < C::CPB * C::H3; e += 256) {
+    if (u + G < U) fetch(u + G);
+#pragma unroll
+    for (int n = 0; n < NE; ++n) {
+      const int e = threadIdx.x + 256 * n;
+      if (e >= C::CPB * C::H3 || unit_cube<NL>(a.g, u, e / C::H3) < 0) continue;
+      // every cell is written (interior ones unchanged), so that whole lines are stored
       const int s2 = e / C::H3, le = e - s2 * C::H3;
       const int I = le % C::H, J = (le / C::H) % C::H, K = le / C::H2;
-      const int base = (s2 * C::H + K) * C::N2 + 2 * J * NL + 2 * I;
-      const T sum = rsum[base] + rsum[base + 1] + rsum[base + NL] + rsum[base + NL + 1];
-      const int c2 = unit_cube<NL>(a.g, u, s2);
-      if (c2 >= 0) a.bc[(size_t)c2 * C::H3 + le] = sum * T(0.125);
+      T corr = T(0);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        if (!(cf[n] >> f & 1)) continue;
+        const int T1 = f < 2 ? J : I, T2 = f < 4 ? K : J;  // coarse tangential position
+        const T* h = hv + (s2 * 6 + f) * C::N2 + (2 * T2) * NL + 2 * T1;
+        corr += (h[0] + h[1]) + (h[NL] + h[NL + 1]);
+      }
+      const T hh = T(a.g.meta[cg[n] / C::H3].h * a.g.hscale);
+      a.bc[cg[n]] = cb[n] - corr * (T(0.125) / (hh * hh));
     }
-    __syncthreads();
-    u = un;
-    c = cn;
+    __syncthreads();  // hv is rewritten for the next unit
+    u += G;
   }
 }
 
@@ -1140,10 +1164,10 @@ hipError_t launchc_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s) {
   return hipSuccess;
 }
 template <typename T>
-hipError_t launchc_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s) {
+hipError_t launchc_rfix(int NL, const RestrictFixArgs<T>& a, hipStream_t s) {
   BCM_COL_NL(NL, {
-    if (a.g.multilevel) return launch_col(kc_restrict<T, NLC, true>, Col<NLC>::CPB, a, s);
-    return launch_col(kc_restrict<T, NLC, false>, Col<NLC>::CPB, a, s);
+    if (a.g.multilevel) return launch_col(kc_rfix<T, NLC, true>, Col<NLC>::CPB, a, s);
+    return launch_col(kc_rfix<T, NLC, false>, Col<NLC>::CPB, a, s);
   });
   return hipSuccess;
 }
@@ -1196,7 +1220,7 @@ hipError_t launch16_correct(const CorrectArgs<TF>& a, hipStream_t s) {
 
 #define BCM_INSTC(T)                                                                  \
   template hipError_t launchc_smooth<T>(int, const SmoothArgs<T>&, hipStream_t);      \
-  template hipError_t launchc_restrict<T>(int, const RestrictArgs<T>&, hipStream_t);  \
+  template hipError_t launchc_rfix<T>(int, const RestrictFixArgs<T>&, hipStream_t);      \
   template hipError_t launchc_apply<T>(int, const ApplyArgs<T>&, hipStream_t);        \
   template hipError_t launchc_resid64<T>(int, const Resid64Args<T>&, hipStream_t);    \
   template hipError_t launchc_ir<T>(int, const IrArgs<T>&, hipStream_t);              \

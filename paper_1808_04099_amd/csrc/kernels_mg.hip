@@ -521,10 +521,6 @@ hipError_t launch_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s) {
   return launchc_smooth<T>(NL, a, s);
 }
 template <typename T>
-hipError_t launch_restrict(int NL, const RestrictArgs<T>& a, hipStream_t s) {
-  return launchc_restrict<T>(NL, a, s);
-}
-template <typename T>
 hipError_t launch_apply(int NL, const ApplyArgs<T>& a, hipStream_t s) {
   return launchc_apply<T>(NL, a, s);
 }
@@ -594,7 +590,6 @@ hipError_t launch_scale(const ScaleArgs& a, hipStream_t s) {
 
 #define BCM_INST_T(T)                                                              \
   template hipError_t launch_smooth<T>(int, const SmoothArgs<T>&, hipStream_t);     \
-  template hipError_t launch_restrict<T>(int, const RestrictArgs<T>&, hipStream_t); \
   template hipError_t launch_apply<T>(int, const ApplyArgs<T>&, hipStream_t);       \
   template hipError_t launch_update<T>(const UpdateArgs<T>&, hipStream_t);          \
   template hipError_t launch_resid64<T>(int, const Resid64Args<T>&, hipStream_t);   \

@@ -247,9 +247,10 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
     sa.sweeps = o.pre_sweeps;
     sa.black_first = 0;
     sa.zero_init = 1;
+    sa.bc = B(l + 1);  // restriction fused into the pre-smoother, completed by kc_rfix
     HIPCHK(timed(P, cls_of("presmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "kc_smooth (pre)");
-    RestrictArgs<T> ra{geom(P, NL), X(l), F(0, l), B(l), B(l + 1)};
-    HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launch_restrict<T>(NL, ra, s); }), "kc_restrict");
+    RestrictFixArgs<T> ra{geom(P, NL), F(0, l), B(l + 1)};
+    HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launchc_rfix<T>(NL, ra, s); }), "kc_rfix");
   }
   if (P->graph && P->g_split > 0) {
     if (int st = coarse_split<T>(P, B(L - 1), X(L - 1), F(1, L - 1), s)) return st;
