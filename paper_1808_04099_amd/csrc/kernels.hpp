@@ -18,6 +18,14 @@ struct Scalars {
   double rr, rr0, bb, zr, zq, pq, alpha, beta, gU, spare[7];
 };
 
+// Host-visible copy of the scalars (pinned, coherent host memory): k_finalize writes the
+// scalars, then the sequence number, so that the host can poll for them instead of waiting
+// for the stream.
+struct ScalarMirror {
+  Scalars sc;
+  uint32_t seq;
+};
+
 struct Geom {  // what every cube-tiled kernel needs
   const CubeMeta* meta;
   const int32_t* launch;
@@ -117,6 +125,8 @@ struct FinalizeArgs {
   Scalars* sc;
   int op;
   int first;
+  ScalarMirror* mirror;  // nullptr: none
+  uint32_t seq;          // written to mirror->seq after the scalars
 };
 enum { OP_BB = 0, OP_RR0 = 1, OP_ZRZQ = 2, OP_PQ = 3, OP_RR = 4, OP_GU = 5 };
 

@@ -103,6 +103,11 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalizeArgs a) {
       sc->gU = t0;
       break;
   }
+  if (a.mirror) {
+    a.mirror->sc = *sc;
+    __threadfence_system();
+    __hip_atomic_store(&a.mirror->seq, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // Conjugate gradients on the one-cell-per-cube level (the cube graph), one workgroup.
