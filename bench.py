@@ -34,7 +34,8 @@ def alg_bytes_per_cell(cls, s, f):
         "postsmooth16": 4 * s + s / 8,   # read x, b, q, coarse correction; write x
         "restrict16": s / 4,             # the restricted residual's cross-cube terms: read, write
         "apply16": 4 * s,                # read z, p; write p, q
-        "update": 6 * s,                 # read x, p, r, q; write x, r
+        "update": 3 * s,                 # read r, q; write r
+        "xupdate": 3 * s,                # read x, p; write x (beside the next V-cycle)
         "resid64": 16 + s,               # read p, b (FP64); write r
         "ir": 8 + s + 8,                 # read p, d; write p
         "force": 7 * f,                  # read u~ (3), alpha; write u* (3)
@@ -212,8 +213,8 @@ def run(args):
     dominant, best = args.kernel, -1.0
     class_ms = {}
     for cls in () if args.kernel else ("presmooth16", "postsmooth16", "restrict16", "apply16",
-                                       "update", "resid64", "ir", "coarse", "force", "div",
-                                       "correct"):
+                                       "update", "xupdate", "resid64", "ir", "coarse", "force",
+                                       "div", "correct"):
         _, _, (nl, tot) = timed_steps(plan, u, a, out, 2, cls)
         nl, tot = nl // 2, tot / 2.0       # per step
         class_ms[cls] = {"launches": nl, "ms_per_step": tot}
@@ -309,7 +310,7 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed_f32fields"])
     ap.add_argument("--kernel", default=None,
                     choices=["presmooth16", "postsmooth16", "restrict16", "apply16", "update",
-                             "resid64", "ir", "force", "div", "correct"],
+                             "xupdate", "resid64", "ir", "force", "div", "correct"],
                     help="timer class for the roofline (skips the per-class survey)")
     ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")

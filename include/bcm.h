@@ -20,10 +20,15 @@
  *     u, alpha, u_s, u_new, face_u and the velocity cotangents in BCM_MIXED_F32FIELDS.
  *     Pressure, the adjoint pressure and g_p are always FP64.
  *   - The library never allocates device memory: bcm_plan_create reports the workspace
- *     size and the caller binds a buffer of at least that size (bcm_plan_bind).
- *   - All GPU work is enqueued on the caller's stream (a hipStream_t passed as void*;
- *     NULL = the default stream).  Calls that return solver results synchronise that
- *     stream at convergence checks; the others are asynchronous.
+ *     size and the caller binds a buffer of at least that size (bcm_plan_bind).  The first
+ *     bind also creates, per plan, a pinned host buffer (136 bytes) for the solver scalars and
+ *     one internal stream with two events; bcm_plan_destroy releases them.
+ *   - All GPU work is ordered on the caller's stream (a hipStream_t passed as void*;
+ *     NULL = the default stream).  Part of each Krylov iteration runs on the plan's
+ *     internal stream, between an event recorded on the caller's stream and one the
+ *     caller's stream waits for, so the caller's stream orders it like its own work.
+ *     Calls that return solver results wait for the solver's scalars at convergence
+ *     checks; the others are asynchronous.
  *   - Return value: BCM_OK (0), a positive warning (outputs valid) or a negative error
  *     (outputs unspecified).  bcm_last_error() returns a thread-local description of the
  *     last error of the calling thread.  No C++ exception crosses this boundary.
@@ -192,7 +197,9 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
 void bcm_plan_destroy(bcm_plan* plan);
 
 /* Bind a caller-owned device buffer (>= workspace_bytes, 256-byte aligned) to the plan and
- * upload the mesh metadata into it on `stream`.  BCM_ERR_WORKSPACE if too small. */
+ * upload the mesh metadata into it on `stream`.  BCM_ERR_WORKSPACE if too small.  The first
+ * bind creates the plan's pinned scalar buffer and internal stream; if either cannot be
+ * created the solver copies its scalars back and keeps all work on the caller's stream. */
 int bcm_plan_bind(bcm_plan* plan, void* d_workspace, size_t bytes, void* stream);
 
 /* One projection step (Sec. 3, forcing -> Poisson -> correction).  The Poisson solve runs to

@@ -13,7 +13,8 @@ namespace bcm {
 
 namespace {
 
-// x += alpha p; r -= alpha q; partial <r, r>_V.  One workgroup per cube.
+// x += alpha p; r -= alpha q; partial <r, r>_V.  One workgroup per cube.  part_sel splits the
+// two updates (the x update can then run beside the next V-cycle).
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   __shared__ double red[8];
@@ -21,13 +22,17 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   const T al = T(a.sc->alpha);
   double rr = 0.0;
   const size_t base = (size_t)c * a.n3;
+  const bool do_x = a.part_sel != 1, do_r = a.part_sel != 2;
   for (int e = threadIdx.x; e < a.n3; e += WG) {
     const size_t g = base + e;
-    st_nt(a.x + g, (a.x_zero ? T(0) : ld_nt(a.x + g)) + al * ld_nt(a.p + g));
-    const T rv = ld_nt(a.r + g) - al * ld_nt(a.q + g);
-    st_nt(a.r + g, rv);
-    rr += double(rv) * double(rv);
+    if (do_x) st_nt(a.x + g, (a.x_zero ? T(0) : ld_nt(a.x + g)) + al * ld_nt(a.p + g));
+    if (do_r) {
+      const T rv = ld_nt(a.r + g) - al * ld_nt(a.q + g);
+      st_nt(a.r + g, rv);
+      rr += double(rv) * double(rv);
+    }
   }
+  if (!do_r) return;
   const double t = block_sum(rr, red);
   if (threadIdx.x == 0) a.part[c] = t * a.meta[c].vol;
 }

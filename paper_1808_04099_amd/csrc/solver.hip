@@ -44,7 +44,7 @@ const char* const kTimerNames[] = {"presmooth16", "presmooth8", "presmooth4", "p
                                    "restrict8", "restrict4", "restrict2", "apply16", "apply8",
                                    "apply4", "apply2", "update", "resid64", "ir", "coarse",
                                    "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
-                                   "export", nullptr};
+                                   "export", "xupdate", nullptr};
 
 int level_index(int NL) { return NL == 16 ? 0 : NL == 8 ? 1 : NL == 4 ? 2 : 3; }
 
@@ -91,6 +91,8 @@ struct bcm_plan {
   size_t o_glev = 0, o_gw = 0, o_perm0 = 0, o_ginv = 0;
   int g_lds = 0;
   int g_split = 0;  // leading graph levels smoothed by the multi-workgroup kernels
+  hipStream_t s2 = nullptr;        // Krylov x updates, beside the next V-cycle
+  hipEvent_t ev_mid = nullptr, ev_x = nullptr;
   ScalarMirror* mirror = nullptr;  // pinned host copy of the scalars (nullptr: copy + sync)
   uint32_t mirror_seq = 0;         // sequence number of the last finalize
   Timer timer;
@@ -251,8 +253,8 @@ int coarse_split(bcm_plan* P, const T* b_in, T* x_out, T* xf_out, hipStream_t s)
 // red-black Gauss-Seidel, then the one-cell-per-cube level (cube-graph multigrid, or the
 // paper's CG with coarse_solver 0).  At level 0 the final smoothing also accumulates <z, r>
 // and (if q_dot) <z, q>.
-template <typename T>
-int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
+template <typename T, class Hook>
+int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s, Hook&& before_coarse) {
   const int L = P->nlev;
   auto X = [&](int l) { return l == 0 ? P->at<T>(P->o_z) : P->at<T>(P->o_x[l]); };
   auto B = [&](int l) { return l == 0 ? P->at<T>(P->o_r) : P->at<T>(P->o_b[l]); };
@@ -273,6 +275,7 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s) {
     RestrictFixArgs<T> ra{geom(P, NL), F(0, l), B(l + 1)};
     HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launchc_rfix<T>(NL, ra, s); }), "kc_rfix");
   }
+  if (const int st = before_coarse()) return st;
   if (P->graph && P->g_split > 0) {
     if (int st = coarse_split<T>(P, B(L - 1), X(L - 1), F(1, L - 1), s)) return st;
   } else if (P->graph) {
@@ -334,33 +337,70 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   T* p = P->at<T>(P->o_p);
   T* q = P->at<T>(P->o_q);
   const bool fcg = P->o.krylov != 0;
+  // The x update of iteration it needs only alpha and p, which stay put until the apply of
+  // iteration it + 1.  It is launched on the second stream when the next V-cycle reaches its
+  // one-cell-per-cube solve, which occupies a single workgroup, and that apply waits for it.
+  UpdateArgs<T> ux{};
+  bool pending = false, in_flight = false;
+  auto launch_x = [&](hipStream_t on) {
+    return timed(P, cls_of("xupdate", 0), on, [&] { return launch_update<T>(ux, on); });
+  };
+  auto start_x = [&]() -> int {
+    if (!pending) return BCM_OK;
+    pending = false;
+    if (!P->s2) {
+      HIPCHK(launch_x(s), "k_update (x)");
+      return BCM_OK;
+    }
+    HIPCHK(hipEventRecord(P->ev_mid, s), "event record");
+    HIPCHK(hipStreamWaitEvent(P->s2, P->ev_mid, 0), "stream wait");
+    HIPCHK(launch_x(P->s2), "k_update (x)");
+    HIPCHK(hipEventRecord(P->ev_x, P->s2), "event record");
+    in_flight = true;
+    return BCM_OK;
+  };
+  auto join_x = [&]() -> int {
+    if (!in_flight) return BCM_OK;
+    in_flight = false;
+    HIPCHK(hipStreamWaitEvent(s, P->ev_x, 0), "stream wait");
+    return BCM_OK;
+  };
+  auto finish = [&](int st) {  // every exit: no x update left behind
+    int e = start_x();
+    if (!e) e = join_x();
+    return st ? st : e;
+  };
   for (int it = 0; it < max_iter; ++it) {
-    int st = vcycle<T>(P, (fcg && it > 0) ? q : nullptr, s);
-    if (st) return st;
-    if ((st = finalize(P, OP_ZRZQ, 0, (fcg && it > 0) ? 1 : -1, nparts, !fcg || it == 0, s))) return st;
+    int st = vcycle<T>(P, (fcg && it > 0) ? q : nullptr, s, start_x);
+    if (st) return finish(st);
+    if ((st = finalize(P, OP_ZRZQ, 0, (fcg && it > 0) ? 1 : -1, nparts, !fcg || it == 0, s))) return finish(st);
+    if ((st = join_x())) return finish(st);
     ApplyArgs<T> aa{geom(P, NL), z, P->at<T>(P->o_zf[1]), p, P->at<T>(P->o_pfk[P->pf_cur]),
                     P->at<T>(P->o_pfk[P->pf_cur ^ 1]), q, P->at<const Scalars>(P->o_sc),
                     (!fcg || it == 0) ? 1 : 0, P->at<double>(P->o_part[2])};
     HIPCHK(timed(P, cls_of("apply", NL), s, [&] { return launch_apply<T>(NL, aa, s); }), "kc_apply");
     P->pf_cur ^= 1;
-    if ((st = finalize(P, OP_PQ, 2, -1, nparts, 0, s))) return st;
+    if ((st = finalize(P, OP_PQ, 2, -1, nparts, 0, s))) return finish(st);
     if (!fcg) {  // stationary iteration: x += z, r -= A z  (alpha = 1)
-      if ((st = finalize(P, OP_PQ, 0, -1, nparts, 0, s))) return st;  // alpha = zr / zr
+      if ((st = finalize(P, OP_PQ, 0, -1, nparts, 0, s))) return finish(st);  // alpha = zr / zr
     }
     UpdateArgs<T> ua{P->at<const CubeMeta>(P->o_meta), P->nc, NL * NL * NL, x, p, r, q,
-                     P->at<const Scalars>(P->o_sc), P->at<double>(P->o_part[0]), x_zero && it == 0};
+                     P->at<const Scalars>(P->o_sc), P->at<double>(P->o_part[0]), x_zero && it == 0, 1};
     HIPCHK(timed(P, cls_of("update", 0), s, [&] { return launch_update<T>(ua, s); }), "k_update");
-    if ((st = finalize(P, OP_RR, 0, -1, P->nc, 0, s))) return st;
-    if ((st = read_scalars(P, hs, s))) return st;
+    ux = ua;
+    ux.part_sel = 2;
+    pending = true;
+    if ((st = finalize(P, OP_RR, 0, -1, P->nc, 0, s))) return finish(st);
+    if ((st = read_scalars(P, hs, s))) return finish(st);
     log.iters++;
     if (!std::isfinite(hs->rr)) {
       set_error("non-finite residual in the Krylov iteration");
-      return BCM_ERR_NONFINITE;
+      return finish(BCM_ERR_NONFINITE);
     }
     log.push(std::sqrt(std::max(hs->rr, 0.0)) * hist_scale);
     if (hs->rr <= thr) break;
   }
-  return BCM_OK;
+  return finish(BCM_OK);
 }
 
 // True FP64 residual of p (faces exported first unless they are current): <r,r>_V (and
@@ -813,6 +853,9 @@ void bcm_plan_destroy(bcm_plan* P) {
   if (!P) return;
   for (hipEvent_t e : P->timer.ev) (void)hipEventDestroy(e);
   if (P->mirror) (void)hipHostFree(P->mirror);
+  if (P->ev_mid) (void)hipEventDestroy(P->ev_mid);
+  if (P->ev_x) (void)hipEventDestroy(P->ev_x);
+  if (P->s2) (void)hipStreamDestroy(P->s2);
   delete P;
 }
 
@@ -845,6 +888,23 @@ int bcm_plan_bind(bcm_plan* P, void* d_ws, size_t bytes, void* stream) {
       std::memset(hm, 0, sizeof(ScalarMirror));
       P->mirror_seq = 0;
     } else {
+      (void)hipGetLastError();
+    }
+  }
+  if (!P->s2) {
+    // second stream (default priority) and its two events for the Krylov x updates; without
+    // them the x updates stay on the caller's stream
+    hipStream_t s2 = nullptr;
+    hipEvent_t e1 = nullptr, e2 = nullptr;
+    if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&e2, hipEventDisableTiming) == hipSuccess) {
+      P->s2 = s2;
+      P->ev_mid = e1;
+      P->ev_x = e2;
+    } else {
+      if (e1) (void)hipEventDestroy(e1);
+      if (s2) (void)hipStreamDestroy(s2);
       (void)hipGetLastError();
     }
   }
