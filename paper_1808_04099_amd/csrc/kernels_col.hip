@@ -1089,6 +1089,12 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
     const double oy_p = j == 15 ? RuleTab<RULE_P>::own(m.kind[3]) : 1.0;
     const double oz_m = RuleTab<RULE_P>::own(m.kind[4]), oz_p = RuleTab<RULE_P>::own(m.kind[5]);
     const int cc = (j + 1) * 18 + (i + 1);
+    // u* of plane k + 1 is loaded while plane k is computed (the loads would otherwise start
+    // only after each plane's barrier)
+    const size_t g0 = (size_t)c * 4096 + t;
+    TF us[3], usn[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) usn[d] = a.unew[d] ? ld_nt(a.ustar[d] + g0) : TF(0);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       double* b = pl[k & 1];
@@ -1099,15 +1105,21 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
         b[0 * 18 + (i + 1)] = hv[2];   // y = -1, x = i
         b[17 * 18 + (i + 1)] = hv[3];  // y = 16, x = i
       }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) us[d] = usn[d];
+      if (k < 15) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) usn[d] = a.unew[d] ? ld_nt(a.ustar[d] + g0 + (k + 1) * 256) : TF(0);
+      }
       __syncthreads();
-      const size_t g = (size_t)c * 4096 + k * 256 + t;
+      const size_t g = g0 + k * 256;
       const double gx = (b[cc + 1] - ox_p * p[k]) - (b[cc - 1] - ox_m * p[k]);
       const double gy = (b[cc + 18] - oy_p * p[k]) - (b[cc - 18] - oy_m * p[k]);
       const double zp = k < 15 ? p[k < 15 ? k + 1 : 15] - p[k] : hv[5] - oz_p * p[k];
       const double zm = k > 0 ? p[k > 0 ? k - 1 : 0] - p[k] : hv[4] - oz_m * p[k];
-      if (a.unew[0]) st_nt(a.unew[0] + g, TF(double(ld_nt(a.ustar[0] + g)) - ch * gx));
-      if (a.unew[1]) st_nt(a.unew[1] + g, TF(double(ld_nt(a.ustar[1] + g)) - ch * gy));
-      if (a.unew[2]) st_nt(a.unew[2] + g, TF(double(ld_nt(a.ustar[2] + g)) - ch * (zp - zm)));
+      if (a.unew[0]) st_nt(a.unew[0] + g, TF(double(us[0]) - ch * gx));
+      if (a.unew[1]) st_nt(a.unew[1] + g, TF(double(us[1]) - ch * gy));
+      if (a.unew[2]) st_nt(a.unew[2] + g, TF(double(us[2]) - ch * (zp - zm)));
     }
     __syncthreads();
   }
