@@ -13,16 +13,17 @@ namespace bcm {
 
 namespace {
 
-// x += alpha p; r -= alpha q; partial <r, r>_V.  One workgroup per cube.  part_sel splits the
-// two updates (the x update can then run beside the next V-cycle).
-template <typename T>
+// x += alpha p; r -= alpha q; partial <r, r>_V.  One workgroup per cube.  SEL splits the two
+// updates (1: r and <r, r> only, 2: x only; 0: both), so that the x update can run beside the
+// next V-cycle.
+template <typename T, int SEL>
 __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   __shared__ double red[8];
   const int c = blockIdx.x;
   const T al = T(a.sc->alpha);
   double rr = 0.0;
   const size_t base = (size_t)c * a.n3;
-  const bool do_x = a.part_sel != 1, do_r = a.part_sel != 2;
+  constexpr bool do_x = SEL != 1, do_r = SEL != 2;
   for (int e = threadIdx.x; e < a.n3; e += WG) {
     const size_t g = base + e;
     if (do_x) st_nt(a.x + g, (a.x_zero ? T(0) : ld_nt(a.x + g)) + al * ld_nt(a.p + g));
@@ -536,7 +537,12 @@ hipError_t launch_apply(int NL, const ApplyArgs<T>& a, hipStream_t s) {
 }
 template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_update<T>), dim3(a.n_cubes), dim3(WG), 0, s, a);
+  if (a.part_sel == 1)
+    hipLaunchKernelGGL((k_update<T, 1>), dim3(a.n_cubes), dim3(WG), 0, s, a);
+  else if (a.part_sel == 2)
+    hipLaunchKernelGGL((k_update<T, 2>), dim3(a.n_cubes), dim3(WG), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_update<T, 0>), dim3(a.n_cubes), dim3(WG), 0, s, a);
   return hipGetLastError();
 }
 template <typename TO>
