@@ -166,3 +166,46 @@ def test_workspace_binding_is_checked():
         assert lib.bcm_plan_bind(ph, ctypes.c_void_p(base), nb.value, stream) == 0
     finally:
         lib.bcm_plan_destroy(ph)
+
+
+def _notched(mesh, removed):
+    """The single-level mesh without the cubes in `removed`; their faces become slip walls."""
+    from bcm_inputs.mesh import BC_SLIP, Mesh
+    keep = [c for c in range(mesh.n_cubes) if c not in removed]
+    new = {c: t for t, c in enumerate(keep)}
+    nbr = -np.ones((len(keep), 6, 4), dtype=np.int32)
+    face_bc = mesh.face_bc[keep].copy()
+    for t, c in enumerate(keep):
+        for f in range(6):
+            o = int(mesh.nbr[c, f, 0])
+            if o < 0:
+                continue
+            if o in new:
+                nbr[t, f, 0] = new[o]
+            else:
+                face_bc[t, f] = BC_SLIP
+    return Mesh(mesh.n, mesh.root_edge, mesh.origin[keep].copy(), mesh.level[keep].copy(), nbr,
+                face_bc, mesh.domain_lo, mesh.domain_hi, {})
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_notched_single_level_mesh(precision):
+    """A channel with a notch (re-entrant edges and corners): the trilinear prolongation's
+    27-neighbourhoods there mix neighbours and walls.  The solve must reach the tolerance in
+    the FP64 operator and agree with the piecewise-constant prolongation's solution."""
+    box = uniform_mesh((4, 3, 2), 0.25, 8, CHANNEL_BC)
+    lo = np.asarray(box.origin)
+    removed = {c for c in range(box.n_cubes) if lo[c, 0] >= 0.5 and lo[c, 1] >= 0.25 and lo[c, 2] >= 0.25}
+    m = _notched(box, removed)
+    log(f"notched mesh: {m.n_cubes} of {box.n_cubes} cubes")
+    b = np.random.default_rng(41).standard_normal(m.n_cells)
+    sols = {}
+    for pro in (0, 1):
+        plan = plan_for(m, precision, prolong=pro)
+        p, rep = plan.poisson_solve(dev(b))
+        assert rep.status == 0, rep
+        r = b - host(plan_for(m).apply_laplacian(p))
+        assert np.linalg.norm(r) <= 1.2e-10 * np.linalg.norm(b)
+        sols[pro] = host(p)
+        log(f"  prolong={pro}: {rep.n_inner} iterations")
+    assert rel_err(sols[1], sols[0]) <= 1e-7
