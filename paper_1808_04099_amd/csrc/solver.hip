@@ -345,10 +345,10 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   auto launch_x = [&](hipStream_t on) {
     return timed(P, cls_of("xupdate", 0), on, [&] { return launch_update<T>(ux, on); });
   };
-  auto start_x = [&]() -> int {
+  auto start_x = [&](bool beside) -> int {
     if (!pending) return BCM_OK;
     pending = false;
-    if (!P->s2) {
+    if (!P->s2 || !beside) {
       HIPCHK(launch_x(s), "k_update (x)");
       return BCM_OK;
     }
@@ -366,12 +366,12 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     return BCM_OK;
   };
   auto finish = [&](int st) {  // every exit: no x update left behind
-    int e = start_x();
-    if (!e) e = join_x();
+    int e = join_x();
+    if (!e) e = start_x(false);  // nothing left to run beside: on the caller's stream
     return st ? st : e;
   };
   for (int it = 0; it < max_iter; ++it) {
-    int st = vcycle<T>(P, (fcg && it > 0) ? q : nullptr, s, start_x);
+    int st = vcycle<T>(P, (fcg && it > 0) ? q : nullptr, s, [&] { return start_x(true); });
     if (st) return finish(st);
     if ((st = finalize(P, OP_ZRZQ, 0, (fcg && it > 0) ? 1 : -1, nparts, !fcg || it == 0, s))) return finish(st);
     if ((st = join_x())) return finish(st);
