@@ -114,7 +114,10 @@ typedef struct {
   int32_t coarse_iters; /* CG iterations on the one-cell-per-cube level (coarse_solver 0),
                            or on the smallest cube-graph level when it is not solved
                            directly (coarse_solver 1; at least 64 are used there)      [10] */
-  int32_t krylov;       /* 1 = flexible CG preconditioned by one V-cycle, 0 = V-cycles  [1] */
+  int32_t krylov;       /* 1 = flexible CG preconditioned by one V-cycle, 0 = V-cycles,
+                           2 = standard preconditioned CG (one field read fewer per
+                           iteration; for preconditioners that do not vary between
+                           iterations, so not with coarse_solver 0)                  [1] */
   int32_t coarse_solver;/* one-cell-per-cube level: 0 = CG only (the paper's scheme),
                            1 = multigrid on the cube graph (octree, then lattice merging;
                            box-shaped domains, otherwise 0 is used)                     [1] */

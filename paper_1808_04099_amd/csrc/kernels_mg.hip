@@ -93,11 +93,18 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalizeArgs a) {
       sc->rr = t0;
       sc->rr0 = t0;
       break;
-    case OP_ZRZQ:
+    case OP_ZRZQ: {
+      const double zr_old = sc->zr;
       sc->zr = t0;
       sc->zq = t1;
-      sc->beta = (a.first || sc->pq == 0.0) ? 0.0 : -t1 / sc->pq;
+      if (a.first)
+        sc->beta = 0.0;
+      else if (a.p1)  // flexible CG: -<z, q_old> / <p_old, q_old>
+        sc->beta = sc->pq == 0.0 ? 0.0 : -t1 / sc->pq;
+      else            // standard preconditioned CG: <z, r> / <z_old, r_old>
+        sc->beta = zr_old == 0.0 ? 0.0 : t0 / zr_old;
       break;
+    }
     case OP_PQ:
       sc->pq = t0;
       sc->alpha = (t0 != 0.0) ? sc->zr / t0 : 0.0;

@@ -336,7 +336,8 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   T* z = P->at<T>(P->o_z);
   T* p = P->at<T>(P->o_p);
   T* q = P->at<T>(P->o_q);
-  const bool fcg = P->o.krylov != 0;
+  const bool fcg = P->o.krylov != 0;    // conjugate gradients (else V-cycle iteration)
+  const bool flex = P->o.krylov == 1;  // flexible CG: beta from <z, q_old>
   // The x update of iteration it needs only alpha and p, which stay put until the apply of
   // iteration it + 1.  It is launched on the second stream when the next V-cycle reaches its
   // one-cell-per-cube solve, which occupies a single workgroup, and that apply waits for it.
@@ -371,9 +372,9 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     return st ? st : e;
   };
   for (int it = 0; it < max_iter; ++it) {
-    int st = vcycle<T>(P, (fcg && it > 0) ? q : nullptr, s, [&] { return start_x(true); });
+    int st = vcycle<T>(P, (flex && it > 0) ? q : nullptr, s, [&] { return start_x(true); });
     if (st) return finish(st);
-    if ((st = finalize(P, OP_ZRZQ, 0, (fcg && it > 0) ? 1 : -1, nparts, !fcg || it == 0, s))) return finish(st);
+    if ((st = finalize(P, OP_ZRZQ, 0, (flex && it > 0) ? 1 : -1, nparts, !fcg || it == 0, s))) return finish(st);
     if ((st = join_x())) return finish(st);
     ApplyArgs<T> aa{geom(P, NL), z, P->at<T>(P->o_zf[1]), p, P->at<T>(P->o_pfk[P->pf_cur]),
                     P->at<T>(P->o_pfk[P->pf_cur ^ 1]), q, P->at<const Scalars>(P->o_sc),
@@ -736,7 +737,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   if (o.precision < BCM_FP64 || o.precision > BCM_MIXED_F32FIELDS || !(o.tol > 0.0) || o.max_iter < 1 ||
       o.max_outer < 1 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.pre_sweeps < 0 ||
       o.post_sweeps < 0 || o.coarse_iters < 0 || o.pre_sweeps > 16 || o.post_sweeps > 16 ||
-      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1 || o.graph_split < -1 ||
+      o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1 || o.graph_split < -1 || o.krylov < 0 || o.krylov > 2 ||
       o.prolong < 0 || o.prolong > 1) {
     set_error("bcm_plan_create: invalid solver options");
     return BCM_ERR_INVALID_ARG;

@@ -140,6 +140,9 @@ def test_plan_workspace_and_options():
         o.prolong = 2
         assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
         lib.bcm_default_opts(ctypes.byref(o))
+        o.krylov = 3
+        assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
+        lib.bcm_default_opts(ctypes.byref(o))
         o.tol = -1.0
         ph = ctypes.c_void_p()
         nb = ctypes.c_size_t()

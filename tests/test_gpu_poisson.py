@@ -107,9 +107,9 @@ def test_split_graph_multigrid_matches_oracle(name, precision):
 @pytest.mark.parametrize("name", ["channel_n16", "multilevel_small_n4"])
 @pytest.mark.parametrize("opts", [dict(coarse_solver=0, max_iter=200), dict(krylov=0, max_iter=200),
                                   dict(coarse_cycles=2), dict(pre_sweeps=1, post_sweeps=3),
-                                  dict(prolong=0)],
+                                  dict(prolong=0), dict(krylov=2)],
                          ids=["paper_cg", "vcycle_iteration", "two_graph_cycles", "sweeps_1_3",
-                              "constant_prolongation"])
+                              "constant_prolongation", "standard_pcg"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solver_variants_match_oracle(name, opts, precision):
     """The paper's scheme (CG capped at coarse_iters on the one-cell-per-cube level, plain
