@@ -226,9 +226,9 @@ template <typename TF> hipError_t launch_adj_gp(int NL, const AdjGpArgs<TF>& a, 
 template <typename TF> hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a, hipStream_t s);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s);
-// Multi-workgroup steps on one large graph level; n = lanes (cubes, nodes of the range, or
-// nodes of the coarser level for G_RESTRICT).
-enum { G_GATHER = 0, G_SMOOTH = 1, G_RESTRICT = 2, G_PROLONG = 3, G_SCATTER = 4 };
+// Multi-workgroup steps on one large graph level; n = lanes (cubes, nodes of the range, nodes
+// of the level for G_RESID, or nodes of the coarser level for G_RESTRICT).
+enum { G_GATHER = 0, G_SMOOTH = 1, G_RESTRICT = 2, G_PROLONG = 3, G_SCATTER = 4, G_RESID = 5 };
 template <typename T> hipError_t launch_g_step(int kind, int n, const GStepArgs<T>& a, hipStream_t s);
 
 // Persistent column kernels of the per-cube levels (kernels_col.hip).  A workgroup handles

@@ -471,18 +471,43 @@ __global__ __launch_bounds__(256) void k_g_smooth(GStepArgs<T> a) {
   L.x[i] = (L.b[i] - g_row(L, i)) / L.diag[i];
 }
 
-// Residual of level g restricted to level g+1 (volume weights), x of level g+1 set to zero.
+// Residual of level g (one lane per node), kept in r for the restriction.
 template <typename T>
-__global__ __launch_bounds__(256) void k_g_resid_restrict(GStepArgs<T> a) {
+__global__ __launch_bounds__(256) void k_g_resid(GStepArgs<T> a) {
+  const GLevel<T>& F = a.lev[a.g];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= F.n) return;
+  F.r[i] = F.b[i] - F.diag[i] * F.x[i] - g_row(F, i);
+}
+
+// Residual of level g restricted to level g+1 (volume weights, every child load issued before
+// use), x of level g+1 set to zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_g_restrict(GStepArgs<T> a) {
   const GLevel<T>& F = a.lev[a.g];
   const GLevel<T>& C = a.lev[a.g + 1];
   const int J = blockIdx.x * 256 + threadIdx.x;
   if (J >= C.n) return;
   T acc = T(0);
-  for (int w = 0; w < C.CW; ++w) {
-    const size_t o = size_t(w) * C.n + J;
-    const int ch = C.child[o];
-    if (ch >= 0) acc += C.child_w[o] * (F.b[ch] - F.diag[ch] * F.x[ch] - g_row(F, ch));
+  if (C.CW <= 8) {
+    int ch[8];
+    T w[8], r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const size_t o = size_t(k) * C.n + J;
+      ch[k] = k < C.CW ? C.child[o] : -1;
+      w[k] = k < C.CW ? C.child_w[o] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = ch[k] >= 0 ? F.r[ch[k]] : T(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += w[k] * r[k];
+  } else {
+    for (int k = 0; k < C.CW; ++k) {
+      const size_t o = size_t(k) * C.n + J;
+      const int ch = C.child[o];
+      if (ch >= 0) acc += C.child_w[o] * F.r[ch];
+    }
   }
   C.b[J] = acc;
   C.x[J] = T(0);
@@ -596,7 +621,8 @@ hipError_t launch_g_step(int kind, int n, const GStepArgs<T>& a, hipStream_t s) 
   switch (kind) {
     case G_GATHER: hipLaunchKernelGGL((k_g_gather<T>), grid, block, 0, s, a); break;
     case G_SMOOTH: hipLaunchKernelGGL((k_g_smooth<T>), grid, block, 0, s, a); break;
-    case G_RESTRICT: hipLaunchKernelGGL((k_g_resid_restrict<T>), grid, block, 0, s, a); break;
+    case G_RESID: hipLaunchKernelGGL((k_g_resid<T>), grid, block, 0, s, a); break;
+    case G_RESTRICT: hipLaunchKernelGGL((k_g_restrict<T>), grid, block, 0, s, a); break;
     case G_PROLONG: hipLaunchKernelGGL((k_g_prolong<T>), grid, block, 0, s, a); break;
     case G_SCATTER: hipLaunchKernelGGL((k_g_scatter<T>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;

@@ -232,6 +232,7 @@ int coarse_split(bcm_plan* P, const T* b_in, T* x_out, T* xf_out, hipStream_t s)
   for (int cy = 0; cy < P->o.coarse_cycles && !st; ++cy) {
     for (int g = 0; g < S && !st; ++g) {
       for (int k = 0; k < pre && !st; ++k) st = sweep(g, true);
+      if (!st) st = step(G_RESID, g, Ls[g].n);
       if (!st) st = step(G_RESTRICT, g, Ls[g + 1].n);
     }
     if (st) break;
