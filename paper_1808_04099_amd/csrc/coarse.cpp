@@ -308,6 +308,19 @@ bool build_coarse_hierarchy(const HostMesh& M, CoarseHierarchy& H, int max_level
       }
       for (; w < W; ++w) L.e_col[size_t(w) * n + p] = p;
     }
+    // packed rows: 6 columns as 16-bit indices when every coupling of the level has one value
+    L.uval = 0.0;
+    L.e_pcol.clear();
+    bool uniform = W == 6 && n <= 65535 && !L.val.empty();
+    for (size_t e = 0; uniform && e < L.val.size(); ++e) uniform = L.val[e] == L.val[0];
+    if (uniform) {
+      L.uval = L.val[0];
+      L.e_pcol.assign(size_t(3) * n, 0u);
+      for (int q = 0; q < 3; ++q)
+        for (int p = 0; p < n; ++p)
+          L.e_pcol[size_t(q) * n + p] = uint32_t(L.e_col[size_t(2 * q) * n + p]) |
+                                        uint32_t(L.e_col[size_t(2 * q + 1) * n + p]) << 16;
+    }
     if (!L.parent.empty()) {
       const std::vector<int32_t>& idc = newid[g + 1];
       L.e_parent.assign(n, 0);

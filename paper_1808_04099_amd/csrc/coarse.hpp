@@ -28,6 +28,10 @@ struct CoarseLevel {
   std::vector<int32_t> e_child;       // [CW][n] children on the finer level, -1 padding
   std::vector<double> e_child_w;      // [CW][n]
   std::vector<int32_t> perm;          // level 0: perm[cube] = device node index
+  // W = 6 levels whose couplings all have one value uval: the columns packed two per word,
+  // [3][n] (low half = even slot; padding = own index), else empty
+  std::vector<uint32_t> e_pcol;
+  double uval = 0.0;
 };
 
 // The last graph level is solved directly (dense inverse) when it has at most this many nodes.
@@ -58,6 +62,8 @@ struct GLevel {
   T* x;
   T* b;
   T* r;
+  const uint32_t* pcol;     // [3][n] packed 16-bit columns (every coupling = uval), or nullptr
+  T uval;
 };
 
 constexpr int kMaxGraphLevels = 12;
@@ -77,9 +83,12 @@ struct CoarseMGArgs {
   double* w;                // CG work space for the bottom level (4 * n_last doubles)
   const T* binv;            // transposed inverse of the bottom operator, or nullptr (CG)
   int lds_bytes;            // dynamic LDS the launch reserves for the lds_* placements
+  int lds_inv;              // byte offset in that LDS where the kernel keeps binv, or -1
 };
 
 constexpr int kGraphLdsBudget = 128 * 1024;
+// Dynamic LDS the single workgroup may reserve in all (the rest of 160 KB is its static LDS).
+constexpr int kGraphLdsTotal = 156 * 1024;
 
 // Argument block of the multi-workgroup graph kernels.
 template <typename T>

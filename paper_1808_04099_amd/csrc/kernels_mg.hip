@@ -218,11 +218,11 @@ __device__ __forceinline__ T g_offdiag(const GLevel<T>& L, const T* x, int i) {
   return acc;
 }
 
-// Width-6 rows (every lattice level): four nodes per lane per pass, all their coupling loads
+// Width-6 rows (every lattice level): two nodes per lane per pass, all their coupling loads
 // issued before any of them is used.
 template <typename T, bool RESID>
 __device__ __forceinline__ void g_pass6(const GLevel<T>& L, int lo, int hi) {
-  constexpr int U = 4;
+  constexpr int U = 2;
   for (int base = lo + threadIdx.x; base < hi; base += U * 1024) {
     int col[U][6];
     T val[U][6], bb[U], dg[U];
@@ -252,6 +252,77 @@ __device__ __forceinline__ void g_pass6(const GLevel<T>& L, int lo, int hi) {
     }
   }
 }
+
+// Packed rows held in registers: lane t owns nodes t + 1024 k (k < K) of a level with at most
+// 1024 K nodes, so that its sweeps and residual read the rows once per kernel, not per pass
+// (the passes of one workgroup are bound by how fast its CU brings rows in: 56 bytes per node
+// in FP32 as columns and values, 16 as packed columns and the diagonal).  Padding slots hold
+// the node's own index and are skipped.
+template <typename T, int K>
+struct GRows {
+  uint32_t pc[K][3];
+  T dg[K];
+  __device__ __forceinline__ void load(const GLevel<T>& L) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = threadIdx.x + 1024 * k;
+      const int ii = i < L.n ? i : 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) pc[k][q] = L.pcol[size_t(q) * L.n + ii];
+      dg[k] = L.diag[ii];
+    }
+  }
+  // nodes [lo, hi) of one colour (RESID false) or all nodes (RESID true), four at a time; a
+  // colour does not couple with itself, so the loads of a group may come before its stores
+  template <bool RESID>
+  __device__ __forceinline__ void pass(const GLevel<T>& L, int lo, int hi) const {
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      constexpr int M = K < 4 ? K : 4;
+      T acc[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int k = k0 + m, i = threadIdx.x + 1024 * k;
+        acc[m] = T(0);
+        if (k >= K || i < lo || i >= hi) continue;
+        // opaque copies: keeps the compiler from unpacking all the columns once, outside
+        // the sweep loops, into 8 times as many registers
+        uint32_t p[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          p[q] = pc[k][q];
+          asm volatile("" : "+v"(p[q]));
+        }
+#pragma unroll
+        for (int w = 0; w < 6; ++w) {
+          const int c = int(w & 1 ? p[w >> 1] >> 16 : p[w >> 1] & 0xffffu);
+          if (c != i) acc[m] += L.uval * L.x[c];
+        }
+        if (RESID) acc[m] = L.b[i] - dg[k] * L.x[i] - acc[m];
+        else acc[m] = (L.b[i] - acc[m]) / dg[k];
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int k = k0 + m, i = threadIdx.x + 1024 * k;
+        if (k >= K || i < lo || i >= hi) continue;
+        if (RESID) L.r[i] = acc[m];
+        else L.x[i] = acc[m];
+      }
+    }
+  }
+  __device__ __forceinline__ void smooth(const GLevel<T>& L, int sweeps, bool forward) const {
+    for (int s = 0; s < sweeps; ++s)
+      for (int cc = 0; cc < L.ncol; ++cc) {
+        const int c = forward ? cc : L.ncol - 1 - cc;
+        pass<false>(L, L.color_off[c], L.color_off[c + 1]);
+        __syncthreads();
+      }
+  }
+  __device__ __forceinline__ void residual(const GLevel<T>& L) const {
+    pass<true>(L, 0, L.n);
+    __syncthreads();
+  }
+};
 
 template <typename T>
 __device__ void g_smooth(const GLevel<T>& L, int sweeps, bool forward) {
@@ -386,6 +457,13 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
   }
   __syncthreads();
   const int G = a.nlev, S = a.start;
+  const T* binv = a.binv;
+  if (binv && a.lds_inv >= 0) {
+    T* sb = reinterpret_cast<T*>(gsm + a.lds_inv);
+    const int nn = lv[G - 1].n * lv[G - 1].n;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) sb[e] = binv[e];
+    binv = sb;
+  }
   if (S == 0) {
     for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
       const int i = a.perm0[c];
@@ -399,15 +477,37 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
       lv[S].x[i] = T(0);
     }
   }
+  // rows of the first levels in registers when they are packed and small enough (two levels
+  // in FP64, three in FP32)
+  constexpr int K0 = sizeof(T) == 4 ? 8 : 4;
+  GRows<T, K0> R0;
+  GRows<T, 1> R1, R2;
+  const bool c0 = S + 1 < G && lv[S].pcol && lv[S].n <= K0 * 1024;
+  const bool c1 = S + 2 < G && lv[S + 1].pcol && lv[S + 1].n <= 1024;
+  const bool c2 = sizeof(T) == 4 && S + 3 < G && lv[S + 2].pcol && lv[S + 2].n <= 1024;
+  if (c0) R0.load(lv[S]);
+  if (c1) R1.load(lv[S + 1]);
+  if (c2) R2.load(lv[S + 2]);
   __syncthreads();
   for (int cy = 0; cy < (S == 0 ? a.cycles : 1); ++cy) {
     for (int g = S; g + 1 < G; ++g) {
-      g_smooth(lv[g], a.pre, true);
-      g_residual(lv[g]);
+      if (g == S && c0) {
+        R0.smooth(lv[g], a.pre, true);
+        R0.residual(lv[g]);
+      } else if (g == S + 1 && c1) {
+        R1.smooth(lv[g], a.pre, true);
+        R1.residual(lv[g]);
+      } else if (g == S + 2 && c2) {
+        R2.smooth(lv[g], a.pre, true);
+        R2.residual(lv[g]);
+      } else {
+        g_smooth(lv[g], a.pre, true);
+        g_residual(lv[g]);
+      }
       g_restrict(lv[g + 1], lv[g].r);
     }
-    if (a.binv)
-      g_direct(lv[G - 1], a.binv);
+    if (binv)
+      g_direct(lv[G - 1], binv);
     else
       g_bottom(lv[G - 1], a.bottom_iters, a.w, red);
     for (int g = G - 2; g >= S; --g) {
@@ -415,7 +515,14 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
       const T* xc = lv[g + 1].x;
       for (int i = threadIdx.x; i < F.n; i += blockDim.x) F.x[i] += xc[F.parent[i]];
       __syncthreads();
-      g_smooth(F, a.post, false);
+      if (g == S && c0)
+        R0.smooth(F, a.post, false);
+      else if (g == S + 1 && c1)
+        R1.smooth(F, a.post, false);
+      else if (g == S + 2 && c2)
+        R2.smooth(F, a.post, false);
+      else
+        g_smooth(F, a.post, false);
     }
   }
   if (S == 0) {
@@ -604,7 +711,7 @@ hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_mg<T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kGraphLdsBudget);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kGraphLdsTotal);
     if (e != hipSuccess) return e;
     attr = true;
   }

@@ -84,12 +84,12 @@ struct bcm_plan {
   // cube-graph multigrid (coarse_solver 1)
   bool graph = false;
   struct GOff {
-    size_t col, val, diag, vol, parent, child, child_w, x, b, r;
+    size_t col, val, diag, vol, parent, child, child_w, x, b, r, pcol;
     int lds_x, lds_b, lds_r;
   };
   std::vector<GOff> g_off;
   size_t o_glev = 0, o_gw = 0, o_perm0 = 0, o_ginv = 0;
-  int g_lds = 0;
+  int g_lds = 0, g_lds_inv = -1;
   int g_split = 0;  // leading graph levels smoothed by the multi-workgroup kernels
   hipStream_t s2 = nullptr;        // Krylov x updates, beside the next V-cycle
   hipEvent_t ev_mid = nullptr, ev_x = nullptr;
@@ -239,7 +239,8 @@ int coarse_split(bcm_plan* P, const T* b_in, T* x_out, T* xf_out, hipStream_t s)
     CoarseMGArgs<T> a{b_in, x_out, xf_out, P->at<const GLevel<T>>(P->o_glev),
                       P->at<const int32_t>(P->o_perm0), int(P->g_off.size()), S, 1, pre, post,
                       std::max(P->o.coarse_iters, 64), P->at<double>(P->o_gw),
-                      P->M->coarse.bottom_inv.empty() ? nullptr : P->at<const T>(P->o_ginv), P->g_lds};
+                      P->M->coarse.bottom_inv.empty() ? nullptr : P->at<const T>(P->o_ginv), P->g_lds,
+                      P->g_lds_inv};
     HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse_mg<T>(a, s); }), "k_coarse_mg");
     for (int g = S - 1; g >= 0 && !st; --g) {
       st = step(G_PROLONG, g, Ls[g].n);
@@ -284,7 +285,8 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s, Hook&& before_coarse) {
                        P->at<const int32_t>(P->o_perm0), int(P->g_off.size()), 0, o.coarse_cycles,
                        2, 2, std::max(o.coarse_iters, 64),  // the last graph level has <= 64 nodes
                        P->at<double>(P->o_gw),
-                       P->M->coarse.bottom_inv.empty() ? nullptr : P->at<const T>(P->o_ginv), P->g_lds};
+                       P->M->coarse.bottom_inv.empty() ? nullptr : P->at<const T>(P->o_ginv), P->g_lds,
+                      P->g_lds_inv};
     HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse_mg<T>(ga, s); }), "k_coarse_mg");
   } else {
     CoarseArgs<T> ca{P->at<const CubeMeta>(P->o_meta), P->nc, double(P->n), B(L - 1), X(L - 1),
@@ -657,6 +659,8 @@ int upload_graph(bcm_plan* P, hipStream_t s) {
     HIPCHK(put(o.diag, conv(L.e_diag).data(), L.e_diag.size() * sizeof(T)), "upload graph diagonal");
     HIPCHK(put(o.vol, conv(L.e_vol).data(), L.e_vol.size() * sizeof(T)), "upload graph volumes");
     HIPCHK(put(o.parent, L.e_parent.data(), L.e_parent.size() * 4), "upload graph parents");
+    if (!L.e_pcol.empty())
+      HIPCHK(put(o.pcol, L.e_pcol.data(), L.e_pcol.size() * 4), "upload packed graph columns");
     if (g > 0) {
       HIPCHK(put(o.child, L.e_child.data(), L.e_child.size() * 4), "upload graph children");
       HIPCHK(put(o.child_w, conv(L.e_child_w).data(), L.e_child_w.size() * sizeof(T)), "upload graph weights");
@@ -681,6 +685,8 @@ int upload_graph(bcm_plan* P, hipStream_t s) {
     d.x = P->at<T>(o.x);
     d.b = P->at<T>(o.b);
     d.r = P->at<T>(o.r);
+    d.pcol = L.e_pcol.empty() ? nullptr : P->at<const uint32_t>(o.pcol);
+    d.uval = T(L.uval);
   }
   HIPCHK(put(P->o_perm0, Ls[0].perm.data(), Ls[0].perm.size() * 4), "upload graph permutation");
   HIPCHK(put(P->o_ginv, conv(P->M->coarse.bottom_inv).data(), P->M->coarse.bottom_inv.size() * sizeof(T)),
@@ -812,6 +818,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
       go.x = take(top, n * Ti);
       go.b = take(top, n * Ti);
       go.r = take(top, n * Ti);
+      go.pcol = L.e_pcol.empty() ? 0 : take(top, L.e_pcol.size() * 4);
       go.lds_x = go.lds_b = go.lds_r = -1;
       P->g_off.push_back(go);
     }
@@ -838,6 +845,15 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
     for (int g = int(Ls.size()) - 1; g >= P->g_split; --g) {
       place(P->g_off[g].lds_b, Ls[g].n);
       place(P->g_off[g].lds_r, Ls[g].n);
+    }
+    // the bottom level's inverse too, when it fits beside them
+    P->g_lds_inv = -1;
+    if (!M.coarse.bottom_inv.empty()) {
+      const int bytes = int((M.coarse.bottom_inv.size() * Ti + 15) / 16 * 16);
+      if (lds + bytes <= kGraphLdsTotal) {
+        P->g_lds_inv = lds;
+        lds += bytes;
+      }
     }
     P->g_lds = lds;
     P->o_glev = take(top, Ls.size() * sizeof(GLevel<double>));
