@@ -273,9 +273,11 @@ struct GRows {
     }
   }
   // nodes [lo, hi) of one colour (RESID false) or all nodes (RESID true), four at a time; a
-  // colour does not couple with itself, so the loads of a group may come before its stores
+  // colour does not couple with itself, so the loads of a group may come before its stores.
+  // x, b and r are the level's arrays in LDS, passed as pointers derived from the kernel's
+  // shared array so that the compiler emits LDS instructions rather than generic ones.
   template <bool RESID>
-  __device__ __forceinline__ void pass(const GLevel<T>& L, int lo, int hi) const {
+  __device__ __forceinline__ void pass(T* x, const T* b, T* r, T uval, int lo, int hi) const {
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += 4) {
       constexpr int M = K < 4 ? K : 4;
@@ -296,30 +298,31 @@ struct GRows {
 #pragma unroll
         for (int w = 0; w < 6; ++w) {
           const int c = int(w & 1 ? p[w >> 1] >> 16 : p[w >> 1] & 0xffffu);
-          if (c != i) acc[m] += L.uval * L.x[c];
+          if (c != i) acc[m] += uval * x[c];
         }
-        if (RESID) acc[m] = L.b[i] - dg[k] * L.x[i] - acc[m];
-        else acc[m] = (L.b[i] - acc[m]) / dg[k];
+        if (RESID) acc[m] = b[i] - dg[k] * x[i] - acc[m];
+        else acc[m] = (b[i] - acc[m]) / dg[k];
       }
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         const int k = k0 + m, i = threadIdx.x + 1024 * k;
         if (k >= K || i < lo || i >= hi) continue;
-        if (RESID) L.r[i] = acc[m];
-        else L.x[i] = acc[m];
+        if (RESID) r[i] = acc[m];
+        else x[i] = acc[m];
       }
     }
   }
-  __device__ __forceinline__ void smooth(const GLevel<T>& L, int sweeps, bool forward) const {
+  __device__ __forceinline__ void smooth(const GLevel<T>& L, T* x, const T* b, int sweeps,
+                                         bool forward) const {
     for (int s = 0; s < sweeps; ++s)
       for (int cc = 0; cc < L.ncol; ++cc) {
         const int c = forward ? cc : L.ncol - 1 - cc;
-        pass<false>(L, L.color_off[c], L.color_off[c + 1]);
+        pass<false>(x, b, nullptr, L.uval, L.color_off[c], L.color_off[c + 1]);
         __syncthreads();
       }
   }
-  __device__ __forceinline__ void residual(const GLevel<T>& L) const {
-    pass<true>(L, 0, L.n);
+  __device__ __forceinline__ void residual(const GLevel<T>& L, T* x, const T* b, T* r) const {
+    pass<true>(x, b, r, L.uval, 0, L.n);
     __syncthreads();
   }
 };
@@ -402,7 +405,7 @@ __device__ void g_bottom(const GLevel<T>& L, int iters, double* w, double* red) 
 // b = volume-weighted restriction of the finer level's residual r; x = 0.  With at most 8
 // children (every merge here is 2x2x2 or a subset) all loads of a node are issued before use.
 template <typename T>
-__device__ void g_restrict(const GLevel<T>& C, const T* r) {
+__device__ __forceinline__ void g_restrict(const GLevel<T>& C, const T* r, T* cb, T* cx) {
   for (int J = threadIdx.x; J < C.n; J += blockDim.x) {
     T acc = T(0);
     if (C.CW <= 8) {
@@ -425,21 +428,27 @@ __device__ void g_restrict(const GLevel<T>& C, const T* r) {
         if (ch >= 0) acc += C.child_w[o] * r[ch];
       }
     }
-    C.b[J] = acc;
-    C.x[J] = T(0);
+    cb[J] = acc;
+    cx[J] = T(0);
   }
   __syncthreads();
 }
 
 // Direct solve of the (small) last level with its inverse precomputed on the host.
 template <typename T>
-__device__ void g_direct(const GLevel<T>& L, const T* inv_t) {
-  const int n = L.n;
+__device__ __forceinline__ void g_direct(int n, const T* inv_t, const T* b, T* x) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     T acc = T(0);
-    for (int j = 0; j < n; ++j) acc += inv_t[j * n + i] * L.b[j];
-    L.x[i] = acc;
+    for (int j = 0; j < n; ++j) acc += inv_t[j * n + i] * b[j];
+    x[i] = acc;
   }
+  __syncthreads();
+}
+
+// x of level g += x of its parent (piecewise-constant prolongation).
+template <typename T>
+__device__ __forceinline__ void g_prolong(const GLevel<T>& F, T* x, const T* xc) {
+  for (int i = threadIdx.x; i < F.n; i += blockDim.x) x[i] += xc[F.parent[i]];
   __syncthreads();
 }
 
@@ -477,50 +486,66 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
       lv[S].x[i] = T(0);
     }
   }
-  // rows of the first levels in registers when they are packed and small enough (two levels
-  // in FP64, three in FP32)
+  // Arrays kept in LDS are addressed through pointers derived from gsm here (not the
+  // generic ones stored in lv), so that the compiler emits LDS instructions for them.
+  auto lds = [&](int off) { return reinterpret_cast<T*>(gsm + off); };
+  auto in_lds = [&](int g) { return lv[g].lds_x >= 0 && lv[g].lds_b >= 0 && lv[g].lds_r >= 0; };
+  // rows of the first levels in registers when they are packed and small enough (one level
+  // in FP64, three in FP32) and their arrays live in LDS
   constexpr int K0 = sizeof(T) == 4 ? 8 : 4;
   GRows<T, K0> R0;
   GRows<T, 1> R1, R2;
-  const bool c0 = S + 1 < G && lv[S].pcol && lv[S].n <= K0 * 1024;
-  const bool c1 = S + 2 < G && lv[S + 1].pcol && lv[S + 1].n <= 1024;
-  const bool c2 = sizeof(T) == 4 && S + 3 < G && lv[S + 2].pcol && lv[S + 2].n <= 1024;
+  const bool c0 = S + 1 < G && lv[S].pcol && lv[S].n <= K0 * 1024 && in_lds(S);
+  const bool c1 = sizeof(T) == 4 && S + 2 < G && lv[S + 1].pcol && lv[S + 1].n <= 1024 && in_lds(S + 1);
+  const bool c2 = sizeof(T) == 4 && S + 3 < G && lv[S + 2].pcol && lv[S + 2].n <= 1024 && in_lds(S + 2);
   if (c0) R0.load(lv[S]);
   if (c1) R1.load(lv[S + 1]);
   if (c2) R2.load(lv[S + 2]);
   __syncthreads();
   for (int cy = 0; cy < (S == 0 ? a.cycles : 1); ++cy) {
     for (int g = S; g + 1 < G; ++g) {
+      const GLevel<T>& L = lv[g];
       if (g == S && c0) {
-        R0.smooth(lv[g], a.pre, true);
-        R0.residual(lv[g]);
+        R0.smooth(L, lds(L.lds_x), lds(L.lds_b), a.pre, true);
+        R0.residual(L, lds(L.lds_x), lds(L.lds_b), lds(L.lds_r));
       } else if (g == S + 1 && c1) {
-        R1.smooth(lv[g], a.pre, true);
-        R1.residual(lv[g]);
+        R1.smooth(L, lds(L.lds_x), lds(L.lds_b), a.pre, true);
+        R1.residual(L, lds(L.lds_x), lds(L.lds_b), lds(L.lds_r));
       } else if (g == S + 2 && c2) {
-        R2.smooth(lv[g], a.pre, true);
-        R2.residual(lv[g]);
+        R2.smooth(L, lds(L.lds_x), lds(L.lds_b), a.pre, true);
+        R2.residual(L, lds(L.lds_x), lds(L.lds_b), lds(L.lds_r));
       } else {
-        g_smooth(lv[g], a.pre, true);
-        g_residual(lv[g]);
+        g_smooth(L, a.pre, true);
+        g_residual(L);
       }
-      g_restrict(lv[g + 1], lv[g].r);
+      const GLevel<T>& C = lv[g + 1];
+      if (L.lds_r >= 0 && C.lds_b >= 0 && C.lds_x >= 0)
+        g_restrict(C, lds(L.lds_r), lds(C.lds_b), lds(C.lds_x));
+      else
+        g_restrict(C, L.r, C.b, C.x);
     }
-    if (binv)
-      g_direct(lv[G - 1], binv);
-    else
-      g_bottom(lv[G - 1], a.bottom_iters, a.w, red);
+    const GLevel<T>& B = lv[G - 1];
+    if (binv) {
+      if (a.lds_inv >= 0 && B.lds_b >= 0 && B.lds_x >= 0)
+        g_direct(B.n, lds(a.lds_inv), lds(B.lds_b), lds(B.lds_x));
+      else
+        g_direct(B.n, binv, B.b, B.x);
+    } else {
+      g_bottom(B, a.bottom_iters, a.w, red);
+    }
     for (int g = G - 2; g >= S; --g) {
       const GLevel<T>& F = lv[g];
-      const T* xc = lv[g + 1].x;
-      for (int i = threadIdx.x; i < F.n; i += blockDim.x) F.x[i] += xc[F.parent[i]];
-      __syncthreads();
+      const GLevel<T>& C = lv[g + 1];
+      if (F.lds_x >= 0 && C.lds_x >= 0)
+        g_prolong(F, lds(F.lds_x), lds(C.lds_x));
+      else
+        g_prolong(F, F.x, C.x);
       if (g == S && c0)
-        R0.smooth(F, a.post, false);
+        R0.smooth(F, lds(F.lds_x), lds(F.lds_b), a.post, false);
       else if (g == S + 1 && c1)
-        R1.smooth(F, a.post, false);
+        R1.smooth(F, lds(F.lds_x), lds(F.lds_b), a.post, false);
       else if (g == S + 2 && c2)
-        R2.smooth(F, a.post, false);
+        R2.smooth(F, lds(F.lds_x), lds(F.lds_b), a.post, false);
       else
         g_smooth(F, a.post, false);
     }
