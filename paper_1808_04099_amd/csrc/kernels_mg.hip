@@ -473,12 +473,22 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
     for (int e = threadIdx.x; e < nn; e += blockDim.x) sb[e] = binv[e];
     binv = sb;
   }
-  if (S == 0) {
+  // Arrays kept in LDS are addressed through pointers derived from gsm here (not the
+  // generic ones stored in lv), so that the compiler emits LDS instructions for them.
+  auto lds = [&](int off) { return reinterpret_cast<T*>(gsm + off); };
+  auto in_lds = [&](int g) { return lv[g].lds_x >= 0 && lv[g].lds_b >= 0 && lv[g].lds_r >= 0; };
+  auto gather = [&](T* b0, T* x0) {
     for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
       const int i = a.perm0[c];
-      lv[0].b[i] = a.b_in[c];
-      lv[0].x[i] = T(0);
+      b0[i] = a.b_in[c];
+      x0[i] = T(0);
     }
+  };
+  if (S == 0) {
+    if (lv[0].lds_b >= 0 && lv[0].lds_x >= 0)
+      gather(lds(lv[0].lds_b), lds(lv[0].lds_x));
+    else
+      gather(lv[0].b, lv[0].x);
   } else {
     const GLevel<T>& L = a.lev[S];  // global buffers of the first level solved here
     for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
@@ -486,10 +496,6 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
       lv[S].x[i] = T(0);
     }
   }
-  // Arrays kept in LDS are addressed through pointers derived from gsm here (not the
-  // generic ones stored in lv), so that the compiler emits LDS instructions for them.
-  auto lds = [&](int off) { return reinterpret_cast<T*>(gsm + off); };
-  auto in_lds = [&](int g) { return lv[g].lds_x >= 0 && lv[g].lds_b >= 0 && lv[g].lds_r >= 0; };
   // rows of the first levels in registers when they are packed and small enough (one level
   // in FP64, three in FP32) and their arrays live in LDS
   constexpr int K0 = sizeof(T) == 4 ? 8 : 4;
@@ -550,13 +556,19 @@ __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
         g_smooth(F, a.post, false);
     }
   }
-  if (S == 0) {
+  auto scatter = [&](const T* x0) {
     for (int c = threadIdx.x; c < lv[0].n; c += blockDim.x) {
-      const T v = lv[0].x[a.perm0[c]];
+      const T v = x0[a.perm0[c]];
       a.x_out[c] = v;
 #pragma unroll
       for (int f = 0; f < 6; ++f) a.xf_out[(size_t)c * face_stride(1) + f] = v;
     }
+  };
+  if (S == 0) {
+    if (lv[0].lds_x >= 0)
+      scatter(lds(lv[0].lds_x));
+    else
+      scatter(lv[0].x);
   } else if (lv[S].x != a.lev[S].x) {
     for (int i = threadIdx.x; i < lv[S].n; i += blockDim.x) a.lev[S].x[i] = lv[S].x[i];
   }
