@@ -24,9 +24,10 @@
  *     bind also creates, per plan, a pinned host buffer (136 bytes) for the solver scalars and
  *     one internal stream with two events; bcm_plan_destroy releases them.
  *   - All GPU work is ordered on the caller's stream (a hipStream_t passed as void*;
- *     NULL = the default stream).  Part of each Krylov iteration runs on the plan's
- *     internal stream, between an event recorded on the caller's stream and one the
- *     caller's stream waits for, so the caller's stream orders it like its own work.
+ *     NULL = the default stream).  On meshes whose cube graph has levels too large for
+ *     one workgroup, part of each Krylov iteration runs on the plan's internal stream,
+ *     between an event recorded on the caller's stream and one the caller's stream waits
+ *     for, so the caller's stream orders it like its own work.
  *     Calls that return solver results wait for the solver's scalars at convergence
  *     checks; the others are asynchronous.
  *   - Return value: BCM_OK (0), a positive warning (outputs valid) or a negative error

@@ -84,6 +84,14 @@ struct CoarseMGArgs {
   const T* binv;            // transposed inverse of the bottom operator, or nullptr (CG)
   int lds_bytes;            // dynamic LDS the launch reserves for the lds_* placements
   int lds_inv;              // byte offset in that LDS where the kernel keeps binv, or -1
+  // Optional vector update x += alpha p carried out by xu_wgs further workgroups of the
+  // same launch, beside the coarse solve (xu_n = 0: none).
+  T* xu_x;
+  const T* xu_p;
+  const double* xu_alpha;
+  size_t xu_n;
+  int xu_zero;              // x starts at zero (not read)
+  int xu_wgs;
 };
 
 constexpr int kGraphLdsBudget = 128 * 1024;

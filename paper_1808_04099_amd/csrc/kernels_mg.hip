@@ -452,8 +452,33 @@ __device__ __forceinline__ void g_prolong(const GLevel<T>& F, T* x, const T* xc)
   __syncthreads();
 }
 
+// The vector update x += alpha p of the workgroups after the first of k_coarse_mg: 16-byte
+// non-temporal accesses, the same arithmetic as k_update.
+template <typename T>
+__device__ __forceinline__ void coarse_side_update(const CoarseMGArgs<T>& a) {
+  typedef T V __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int W = 16 / sizeof(T);
+  const T al = T(*a.xu_alpha);
+  const size_t nv = a.xu_n / W;
+  const size_t first = size_t(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x - 1) * blockDim.x;
+  V* xv = reinterpret_cast<V*>(a.xu_x);
+  const V* pv = reinterpret_cast<const V*>(a.xu_p);
+  for (size_t e = first; e < nv; e += stride) {
+    const V p = __builtin_nontemporal_load(pv + e);
+    const V x = a.xu_zero ? V(T(0)) : __builtin_nontemporal_load(xv + e);
+    __builtin_nontemporal_store(x + al * p, xv + e);
+  }
+  for (size_t e = nv * W + first; e < a.xu_n; e += stride)
+    a.xu_x[e] = (a.xu_zero ? T(0) : a.xu_x[e]) + al * a.xu_p[e];
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_coarse_mg(CoarseMGArgs<T> a) {
+  if (blockIdx.x > 0) {  // the side update (only launched with xu_n > 0)
+    coarse_side_update(a);
+    return;
+  }
   extern __shared__ __align__(16) unsigned char gsm[];
   __shared__ double red[16];
   __shared__ GLevel<T> lv[kMaxGraphLevels];
@@ -752,7 +777,8 @@ hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_coarse_mg<T>), dim3(1), dim3(1024), a.lds_bytes, s, a);
+  const int grid = a.xu_n > 0 ? 1 + (a.xu_wgs > 1 ? a.xu_wgs : 1) : 1;
+  hipLaunchKernelGGL((k_coarse_mg<T>), dim3(grid), dim3(1024), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_coarse_mg<float>(const CoarseMGArgs<float>&, hipStream_t);

@@ -93,6 +93,7 @@ struct bcm_plan {
   int g_split = 0;  // leading graph levels smoothed by the multi-workgroup kernels
   hipStream_t s2 = nullptr;        // Krylov x updates, beside the next V-cycle
   hipEvent_t ev_mid = nullptr, ev_x = nullptr;
+  int side_wgs = 1;                // workgroups of a vector update carried by the coarse launch
   ScalarMirror* mirror = nullptr;  // pinned host copy of the scalars (nullptr: copy + sync)
   uint32_t mirror_seq = 0;         // sequence number of the last finalize
   Timer timer;
@@ -277,8 +278,8 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s, Hook&& before_coarse) {
     RestrictFixArgs<T> ra{geom(P, NL), F(0, l), B(l + 1)};
     HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launchc_rfix<T>(NL, ra, s); }), "kc_rfix");
   }
-  if (const int st = before_coarse()) return st;
   if (P->graph && P->g_split > 0) {
+    if (const int st = before_coarse(nullptr)) return st;
     if (int st = coarse_split<T>(P, B(L - 1), X(L - 1), F(1, L - 1), s)) return st;
   } else if (P->graph) {
     CoarseMGArgs<T> ga{B(L - 1), X(L - 1), F(1, L - 1), P->at<const GLevel<T>>(P->o_glev),
@@ -287,8 +288,10 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s, Hook&& before_coarse) {
                        P->at<double>(P->o_gw),
                        P->M->coarse.bottom_inv.empty() ? nullptr : P->at<const T>(P->o_ginv), P->g_lds,
                       P->g_lds_inv};
+    if (const int st = before_coarse(&ga)) return st;  // may hand it a vector update to carry
     HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse_mg<T>(ga, s); }), "k_coarse_mg");
   } else {
+    if (const int st = before_coarse(nullptr)) return st;
     CoarseArgs<T> ca{P->at<const CubeMeta>(P->o_meta), P->nc, double(P->n), B(L - 1), X(L - 1),
                      F(1, L - 1), P->at<double>(P->o_cw), o.coarse_iters};
     HIPCHK(timed(P, cls_of("coarse", 0), s, [&] { return launch_coarse<T>(ca, s); }), "k_coarse");
@@ -349,9 +352,18 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   auto launch_x = [&](hipStream_t on) {
     return timed(P, cls_of("xupdate", 0), on, [&] { return launch_update<T>(ux, on); });
   };
-  auto start_x = [&](bool beside) -> int {
+  auto start_x = [&](bool beside, CoarseMGArgs<T>* carrier) -> int {
     if (!pending) return BCM_OK;
     pending = false;
+    if (beside && carrier) {  // the single-workgroup coarse solve's launch carries it
+      carrier->xu_x = ux.x;
+      carrier->xu_p = ux.p;
+      carrier->xu_alpha = &ux.sc->alpha;
+      carrier->xu_n = size_t(ux.n_cubes) * size_t(ux.n3);
+      carrier->xu_zero = ux.x_zero;
+      carrier->xu_wgs = P->side_wgs;
+      return BCM_OK;
+    }
     if (!P->s2 || !beside) {
       HIPCHK(launch_x(s), "k_update (x)");
       return BCM_OK;
@@ -371,11 +383,12 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   };
   auto finish = [&](int st) {  // every exit: no x update left behind
     int e = join_x();
-    if (!e) e = start_x(false);  // nothing left to run beside: on the caller's stream
+    if (!e) e = start_x(false, nullptr);  // nothing left to run beside: on the caller's stream
     return st ? st : e;
   };
   for (int it = 0; it < max_iter; ++it) {
-    int st = vcycle<T>(P, (flex && it > 0) ? q : nullptr, s, [&] { return start_x(true); });
+    int st = vcycle<T>(P, (flex && it > 0) ? q : nullptr, s,
+                       [&](CoarseMGArgs<T>* carrier) { return start_x(true, carrier); });
     if (st) return finish(st);
     if ((st = finalize(P, OP_ZRZQ, 0, (flex && it > 0) ? 1 : -1, nparts, !fcg || it == 0, s))) return finish(st);
     if ((st = join_x())) return finish(st);
@@ -925,6 +938,16 @@ int bcm_plan_bind(bcm_plan* P, void* d_ws, size_t bytes, void* stream) {
       if (s2) (void)hipStreamDestroy(s2);
       (void)hipGetLastError();
     }
+  }
+  {
+    // a carried vector update gets every CU but the coarse solve's (one workgroup per CU: the
+    // launch reserves the coarse solve's LDS for each)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 1)
+      P->side_wgs = cus - 1;
+    else
+      (void)hipGetLastError();
   }
   if (P->graph) return P->inner32 ? upload_graph<float>(P, s) : upload_graph<double>(P, s);
   return BCM_OK;
