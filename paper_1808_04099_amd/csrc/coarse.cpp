@@ -15,6 +15,8 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
+#include <tuple>
 #include <unordered_map>
 
 #include "bcm_internal.hpp"
@@ -119,6 +121,36 @@ void build_level(CoarseLevel& L, const std::vector<Key>& keys, const int dims[3]
     while (used & (1ull << c)) ++c;
     colour[t] = c;
     ncol = std::max(ncol, c + 1);
+  }
+  if (ncol > 2) {
+    // not bipartite (2:1 interfaces): try saturation-degree order (DSATUR), which usually
+    // needs fewer colours, i.e. fewer multi-workgroup launches per sweep
+    std::vector<int> dcol(n, -1), deg(n);
+    std::vector<uint64_t> sat(n, 0);
+    std::set<std::tuple<int, int, int>> pq;  // (saturation, degree, node), largest first
+    for (int t = 0; t < n; ++t) {
+      deg[t] = int(adj[t].size());
+      pq.insert({0, deg[t], t});
+    }
+    int dn = 0;
+    while (!pq.empty()) {
+      const int t = std::get<2>(*std::prev(pq.end()));
+      pq.erase(std::prev(pq.end()));
+      int c = 0;
+      while (c < 64 && (sat[t] >> c & 1)) ++c;
+      dcol[t] = c;
+      dn = std::max(dn, c + 1);
+      for (int o : adj[t]) {
+        if (dcol[o] >= 0 || c >= 64 || (sat[o] >> c & 1)) continue;
+        pq.erase({__builtin_popcountll(sat[o]), deg[o], o});
+        sat[o] |= 1ull << c;
+        pq.insert({__builtin_popcountll(sat[o]), deg[o], o});
+      }
+    }
+    if (dn < ncol) {
+      colour = dcol;
+      ncol = dn;
+    }
   }
   L.order.clear();
   L.color_off.assign(1, 0);
