@@ -130,6 +130,10 @@ typedef struct {
   int32_t prolong;      /* per-cube multigrid prolongation: 1 = trilinear over the cube's
                            27-neighbourhood (single-level meshes; meshes with 2:1 faces use
                            0), 0 = piecewise constant                                   [1] */
+  int32_t check_every;  /* Krylov iterations per convergence check (>= 1).  Each check
+                           waits for the solver's scalars on the host; between checks the
+                           iterations are enqueued without waiting, so a solve may run up
+                           to check_every - 1 iterations past convergence                [1] */
 } bcm_solver_opts;
 
 /* Per-call solver report (host memory). */
@@ -139,7 +143,8 @@ typedef struct {
   int32_t n_inner;       /* total Krylov (or V-cycle) iterations */
   double final_rel_res;  /* true FP64 relative residual of the returned pressure */
   double* history;       /* caller array of history_cap doubles, or NULL: relative residual
-                            after every iteration (inner ones rescaled to the FP64 RHS) */
+                            at every convergence check (every check_every iterations; inner
+                            ones rescaled to the FP64 RHS) */
   int32_t history_cap;
   int32_t history_len;   /* entries written */
 } bcm_report;

@@ -24,7 +24,7 @@ class SolverOpts(ctypes.Structure):
                 ("max_outer", c_int32), ("inner_tol", c_double), ("pre_sweeps", c_int32),
                 ("post_sweeps", c_int32), ("coarse_iters", c_int32), ("krylov", c_int32),
                 ("coarse_solver", c_int32), ("coarse_cycles", c_int32),
-                ("graph_split", c_int32), ("prolong", c_int32)]
+                ("graph_split", c_int32), ("prolong", c_int32), ("check_every", c_int32)]
 
 
 class Report(ctypes.Structure):

@@ -408,8 +408,10 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     ux.part_sel = 2;
     pending = true;
     if ((st = finalize(P, OP_RR, 0, -1, P->nc, 0, s))) return finish(st);
-    if ((st = read_scalars(P, hs, s))) return finish(st);
     log.iters++;
+    // convergence checks every check_every iterations and at the last one
+    if ((it + 1) % P->o.check_every != 0 && it + 1 < max_iter) continue;
+    if ((st = read_scalars(P, hs, s))) return finish(st);
     if (!std::isfinite(hs->rr)) {
       set_error("non-finite residual in the Krylov iteration");
       return finish(BCM_ERR_NONFINITE);
@@ -740,6 +742,7 @@ void bcm_default_opts(bcm_solver_opts* o) {
   o->coarse_cycles = 1;
   o->graph_split = -1;
   o->prolong = 1;
+  o->check_every = 1;
 }
 
 int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan** out,
@@ -758,7 +761,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
       o.max_outer < 1 || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.pre_sweeps < 0 ||
       o.post_sweeps < 0 || o.coarse_iters < 0 || o.pre_sweeps > 16 || o.post_sweeps > 16 ||
       o.coarse_solver < 0 || o.coarse_solver > 1 || o.coarse_cycles < 1 || o.graph_split < -1 || o.krylov < 0 || o.krylov > 2 ||
-      o.prolong < 0 || o.prolong > 1) {
+      o.prolong < 0 || o.prolong > 1 || o.check_every < 1) {
     set_error("bcm_plan_create: invalid solver options");
     return BCM_ERR_INVALID_ARG;
   }

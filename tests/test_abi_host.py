@@ -131,7 +131,7 @@ def test_plan_workspace_and_options():
         o = L.SolverOpts()
         lib.bcm_default_opts(ctypes.byref(o))
         assert (o.max_iter, o.max_outer, o.coarse_solver, o.coarse_cycles, o.graph_split,
-                o.prolong) == (50, 10, 1, 1, -1, 1)
+                o.prolong, o.check_every) == (50, 10, 1, 1, -1, 1, 1)
         o.graph_split = -2
         ph = ctypes.c_void_p()
         nb = ctypes.c_size_t()
@@ -141,6 +141,9 @@ def test_plan_workspace_and_options():
         assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
         lib.bcm_default_opts(ctypes.byref(o))
         o.krylov = 3
+        assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
+        lib.bcm_default_opts(ctypes.byref(o))
+        o.check_every = 0
         assert lib.bcm_plan_create(mh, ctypes.byref(o), ctypes.byref(ph), ctypes.byref(nb)) == -1
         lib.bcm_default_opts(ctypes.byref(o))
         o.tol = -1.0

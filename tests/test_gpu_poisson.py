@@ -107,9 +107,9 @@ def test_split_graph_multigrid_matches_oracle(name, precision):
 @pytest.mark.parametrize("name", ["channel_n16", "multilevel_small_n4"])
 @pytest.mark.parametrize("opts", [dict(coarse_solver=0, max_iter=200), dict(krylov=0, max_iter=200),
                                   dict(coarse_cycles=2), dict(pre_sweeps=1, post_sweeps=3),
-                                  dict(prolong=0), dict(krylov=2)],
+                                  dict(prolong=0), dict(krylov=2), dict(check_every=3)],
                          ids=["paper_cg", "vcycle_iteration", "two_graph_cycles", "sweeps_1_3",
-                              "constant_prolongation", "standard_pcg"])
+                              "constant_prolongation", "standard_pcg", "checks_every_3"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solver_variants_match_oracle(name, opts, precision):
     """The paper's scheme (CG capped at coarse_iters on the one-cell-per-cube level, plain
@@ -124,6 +124,26 @@ def test_solver_variants_match_oracle(name, opts, precision):
     log(f"  iters={rep.n_inner} outer={rep.n_outer} oracle={rr:.3e}")
     assert rep.status == 0 and rr <= 1.2e-10
     assert rel_err(p, fv.solve(b)) <= 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_check_every_reads_back_less_often(precision):
+    """check_every = 3 tests convergence every third Krylov iteration: the solve still reaches
+    the tolerance, with fewer history entries (one per check) than checking every iteration,
+    and every inner solve ends on a check."""
+    m = _meshes()["channel_n16"]
+    fv = FVMesh(m)
+    b = np.random.default_rng(37).standard_normal(m.n_cells)
+    p1, r1 = plan_for(m, precision).poisson_solve(dev(b))
+    p3, r3 = plan_for(m, precision, check_every=3).poisson_solve(dev(b))
+    log(f"check_every 1: {r1.n_inner} its, {len(r1.history)} entries; "
+        f"3: {r3.n_inner} its, {len(r3.history)} entries ({precision})")
+    assert r1.status == 0 and r3.status == 0
+    assert fv.residual_norm(host(p3), b) <= 1.2e-10
+    assert len(r3.history) < len(r1.history)
+    # one entry per outer residual plus one per check (ceil(inner iterations / 3) per solve)
+    assert len(r3.history) <= r3.n_outer + 1 + (r3.n_inner + 2 * (r3.n_outer + 1)) // 3
+    assert rel_err(host(p3), fv.solve(b)) <= 1e-7
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
