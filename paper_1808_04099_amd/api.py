@@ -100,7 +100,7 @@ class Plan:
 
     precision: "fp64", "mixed" or "mixed_f32fields"; other keyword arguments override the
     fields of bcm_solver_opts (tol, max_iter, max_outer, inner_tol, pre_sweeps, post_sweeps,
-    coarse_iters, krylov, coarse_solver, coarse_cycles, graph_split, prolong)."""
+    coarse_iters, krylov, coarse_solver, coarse_cycles, graph_split, prolong, check_every)."""
 
     def __init__(self, mesh: Mesh, precision="fp64", device="cuda", **opts):
         self._lib = L.load()
