@@ -355,7 +355,9 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   auto start_x = [&](bool beside, CoarseMGArgs<T>* carrier) -> int {
     if (!pending) return BCM_OK;
     pending = false;
-    if (beside && carrier) {  // the single-workgroup coarse solve's launch carries it
+    const bool vec_ok = (reinterpret_cast<uintptr_t>(ux.x) | reinterpret_cast<uintptr_t>(ux.p)) % 16 == 0;
+    if (beside && carrier && vec_ok) {  // the single-workgroup coarse solve's launch carries it
+                                        // (16-byte accesses: x and p must be 16-byte aligned)
       carrier->xu_x = ux.x;
       carrier->xu_p = ux.p;
       carrier->xu_alpha = &ux.sc->alpha;

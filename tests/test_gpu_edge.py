@@ -146,6 +146,22 @@ def test_runs_on_the_callers_stream():
     assert np.array_equal(p.numpy(), ref_p)
 
 
+def test_unaligned_pressure_field_gives_the_same_solution():
+    """An FP64 solve into a pressure field that is not 16-byte aligned (a view one element
+    into a buffer) gives bit-for-bit the result of an aligned one: the Krylov x update then
+    runs as its own kernel instead of inside the coarse-solve launch."""
+    m = uniform_mesh((4, 2, 2), 0.25, 16, CHANNEL_BC)
+    b = dev(np.random.default_rng(41).standard_normal(m.n_cells))
+    plan = plan_for(m, "fp64")
+    p_ref, rep_ref = plan.poisson_solve(b)
+    buf = torch.zeros(m.n_cells + 1, dtype=torch.float64, device="cuda")
+    p_off = buf[1:]
+    assert p_off.data_ptr() % 16 == 8
+    p_got, rep = plan.poisson_solve(b, p=p_off)
+    assert rep.status == 0 and rep.n_inner == rep_ref.n_inner
+    assert np.array_equal(host(p_got), host(p_ref))
+
+
 def test_workspace_binding_is_checked():
     """bcm_plan_bind refuses a workspace smaller than reported or not 256-byte aligned."""
     import ctypes
