@@ -51,6 +51,10 @@ typedef struct bcm_plan bcm_plan;
 enum {
   BCM_OK = 0,
   BCM_NOT_CONVERGED = 1,       /* tolerance not reached within the iteration limits */
+  BCM_STAGNATED = 2,           /* tolerance not reached: the true residual stopped decreasing
+                                  (an FP64 Krylov pass, or two refinement steps in a row, did
+                                  not halve it); the outputs are valid and final_rel_res is
+                                  their true residual */
   BCM_ERR_INVALID_ARG = -1,
   BCM_ERR_INVALID_MESH = -2,
   BCM_ERR_WORKSPACE = -3,      /* no workspace bound, or the bound one is too small */
@@ -106,7 +110,8 @@ typedef struct {
   int32_t precision;    /* BCM_FP64 / BCM_MIXED / BCM_MIXED_F32FIELDS            [BCM_FP64] */
   double tol;           /* target ||b - A p||_V / ||b||_V, evaluated in FP64       [1e-10] */
   int32_t max_iter;     /* Krylov iterations per solve (FP64 mode) / per inner solve   [50] */
-  int32_t max_outer;    /* mixed modes: FP64 refinement steps                          [10] */
+  int32_t max_outer;    /* mixed modes: FP64 refinement steps; FP64 mode: Krylov solves
+                           restarted from the true residual (both share max_iter)      [10] */
   double inner_tol;     /* mixed modes: residual reduction asked of each FP32 inner solve
                            (the last one only as much as tol still needs); FP32 rounding
                            of the operator limits what one refinement step gains   [1e-3] */
@@ -184,9 +189,13 @@ typedef struct {
 
 typedef struct {
   void* g_u[3];          /* cotangent of u~ (written) */
-  void* g_alpha;         /* cotangent of alpha (written; ignored when alpha is NULL) */
-  double g_U_in;         /* cotangent of U_in (host scalar, written) */
+  void* g_alpha;         /* cotangent of alpha (written, or accumulated; ignored when alpha is
+                            NULL) */
+  double g_U_in;         /* cotangent of U_in (host scalar, written, or accumulated) */
   double* lambda;        /* optional: adjoint pressure A^{-T}(...) (device FP64) or NULL */
+  int32_t accumulate;    /* 0: g_alpha and g_U_in are overwritten; 1: this step's cotangents
+                            are added to what they hold (the reverse sweep of a multi-step
+                            objective sums them over the steps) */
 } bcm_adjoint_out;
 
 /* Fill opts with the defaults listed in bcm_solver_opts. */
@@ -212,8 +221,9 @@ void bcm_plan_destroy(bcm_plan* plan);
 int bcm_plan_bind(bcm_plan* plan, void* d_workspace, size_t bytes, void* stream);
 
 /* One projection step (Sec. 3, forcing -> Poisson -> correction).  The Poisson solve runs to
- * opts.tol; BCM_NOT_CONVERGED if the limits are hit first (outputs valid), BCM_ERR_NONFINITE
- * if a residual norm is not finite.  report may be NULL. */
+ * opts.tol; BCM_NOT_CONVERGED if the limits are hit first and BCM_STAGNATED if the residual
+ * stops decreasing first (outputs valid in both cases), BCM_ERR_NONFINITE if a residual norm
+ * is not finite.  report may be NULL. */
 int bcm_project(bcm_plan* plan, const bcm_project_in* in, bcm_project_out* out,
                 bcm_report* report, void* stream);
 
@@ -227,6 +237,21 @@ int bcm_project_recompute(bcm_plan* plan, const bcm_project_in* in, const double
  * interpolation, divergence and forcing.  Solver options as for the forward call. */
 int bcm_project_adjoint(bcm_plan* plan, const bcm_adjoint_in* in, bcm_adjoint_out* out,
                         bcm_report* report, void* stream);
+
+/* Objective of the differentiable multi-step projection: the kinetic energy of a cell-centred
+ * velocity field, J = (rho/2) sum_i V_i |u_i|^2 with V_i = h_i^3 the cell volume (the paper
+ * states no normalisation for it; this is the discrete form on the mesh's cells), summed in
+ * FP64 with a reduction whose order does not depend on the run (bitwise reproducible).
+ *   u       three device fields of the plan's field type (cube-major, n_cubes * n^3 each)
+ *   rho     density (> 0)
+ *   J       host double, or NULL to skip the sum (then the call does not wait for the GPU)
+ *   g_u     NULL, or three device fields of the field type that receive the cotangent
+ *           g_scale * dJ/du_i = g_scale * rho * V_i * u_i (the seed of the reverse sweep)
+ * Errors: BCM_ERR_INVALID_ARG (NULL field, rho <= 0, non-finite g_scale), BCM_ERR_WORKSPACE
+ * (no workspace bound), BCM_ERR_NONFINITE (J not finite).  Uses the plan's workspace, so it
+ * must not overlap other calls on the plan. */
+int bcm_kinetic_energy(bcm_plan* plan, const void* const u[3], double rho, double g_scale,
+                       double* J, void* const g_u[3], void* stream);
 
 /* Solve the pressure Poisson equation A p = b (Sec. 3) for a device FP64 right-hand side;
  * d_p holds the initial guess on entry if use_guess != 0 (else zero) and the solution on

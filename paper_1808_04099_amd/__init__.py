@@ -8,7 +8,7 @@ The compiled library must exist (python -m paper_1808_04099_amd.build); there is
 fallback.
 """
 from .api import BCMError, Mesh, Plan, SolveReport, timing_names
-from .autograd import MultiStepProjection, Projection, kinetic_energy
+from .autograd import KineticEnergy, MultiStepProjection, Projection, kinetic_energy
 
 __all__ = ["BCMError", "Mesh", "Plan", "SolveReport", "timing_names", "Projection",
-           "MultiStepProjection", "kinetic_energy"]
+           "MultiStepProjection", "KineticEnergy", "kinetic_energy"]

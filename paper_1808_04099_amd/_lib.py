@@ -8,7 +8,7 @@ from ctypes import POINTER, c_char_p, c_double, c_int, c_int8, c_int32, c_int64,
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbcm.so")
 
-BCM_OK, BCM_NOT_CONVERGED = 0, 1
+BCM_OK, BCM_NOT_CONVERGED, BCM_STAGNATED = 0, 1, 2
 BCM_FP64, BCM_MIXED, BCM_MIXED_F32FIELDS = 0, 1, 2
 PRECISIONS = {"fp64": BCM_FP64, "mixed": BCM_MIXED, "mixed_f32fields": BCM_MIXED_F32FIELDS}
 
@@ -52,7 +52,7 @@ class AdjointIn(ctypes.Structure):
 
 class AdjointOut(ctypes.Structure):
     _fields_ = [("g_u", c_void_p * 3), ("g_alpha", c_void_p), ("g_U_in", c_double),
-                ("lambda_", c_void_p)]
+                ("lambda_", c_void_p), ("accumulate", c_int32)]
 
 
 EXPORTS = {
@@ -72,6 +72,8 @@ EXPORTS = {
     "bcm_poisson_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_int, POINTER(Report),
                                   c_void_p]),
     "bcm_apply_laplacian": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "bcm_kinetic_energy": (c_int, [c_void_p, POINTER(c_void_p), c_double, c_double,
+                                   POINTER(c_double), POINTER(c_void_p), c_void_p]),
     "bcm_timing_enable": (c_int, [c_void_p, c_char_p]),
     "bcm_timing_read": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_double)]),
     "bcm_timing_name": (c_char_p, [c_int]),

@@ -206,9 +206,11 @@ class Plan:
         return out
 
     def project_adjoint(self, u, alpha, g_u_new, U_in, dt, rho, us=(0.0, 0.0, 0.0), g_p=None,
-                        want_lambda=False, history=4096):
+                        want_lambda=False, history=4096, g_alpha=None, g_U_in=0.0,
+                        accumulate=False):
         """Reverse-mode derivative of project; returns (g_u [3], g_alpha, g_U_in, report,
-        lambda or None)."""
+        lambda or None).  With accumulate=True the step's cotangents of alpha and U_in are
+        added (in the library) to the given g_alpha field and g_U_in value."""
         u = [self._field(x, f"u[{d}]") for d, x in enumerate(u)]
         alpha = self._field(alpha, "alpha")
         g = [self._field(x, f"g_u_new[{d}]") for d, x in enumerate(g_u_new)]
@@ -216,7 +218,14 @@ class Plan:
         us_t = [self._field(x, "us") if torch.is_tensor(x) else None for x in us]
         usc = [0.0 if torch.is_tensor(x) else float(x) for x in us]
         g_u = [self.empty() for _ in range(3)]
-        g_alpha = self.empty() if alpha is not None else None
+        if alpha is None:
+            g_alpha = None
+        elif g_alpha is None:
+            if accumulate:
+                raise ValueError("accumulate=True needs the g_alpha field to add to")
+            g_alpha = self.empty()
+        else:
+            g_alpha = self._field(g_alpha, "g_alpha")
         lam = self.empty(torch.float64) if want_lambda else None
         ain = L.AdjointIn((ctypes.c_void_p * 3)(*[x.data_ptr() for x in u]), _ptr(alpha).value,
                           (ctypes.c_void_p * 3)(*[t.data_ptr() if t is not None else None
@@ -224,12 +233,27 @@ class Plan:
                           (ctypes.c_double * 3)(*usc), float(U_in), float(dt), float(rho),
                           (ctypes.c_void_p * 3)(*[x.data_ptr() for x in g]), _ptr(g_p).value)
         aout = L.AdjointOut((ctypes.c_void_p * 3)(*[x.data_ptr() for x in g_u]),
-                            _ptr(g_alpha).value, 0.0, _ptr(lam).value)
+                            _ptr(g_alpha).value, float(g_U_in) if accumulate else 0.0,
+                            _ptr(lam).value, 1 if accumulate else 0)
         rep, hist = _report(history)
         st = self._lib.bcm_project_adjoint(self.handle, ctypes.byref(ain), ctypes.byref(aout),
                                            ctypes.byref(rep), _stream())
         _check(st, "bcm_project_adjoint")
         return g_u, g_alpha, float(aout.g_U_in), _unpack(rep, hist), lam
+
+    def kinetic_energy(self, u, rho, g_scale=None, want_J=True):
+        """J = (rho/2) sum_i V_i |u_i|^2 (host float, or None with want_J=False) and, when
+        g_scale is given, the seed cotangent g_scale * rho * V * u (three fields; else None)."""
+        u = [self._field(x, f"u[{d}]") for d, x in enumerate(u)]
+        seed = [self.empty() for _ in range(3)] if g_scale is not None else None
+        J = ctypes.c_double(0.0)
+        st = self._lib.bcm_kinetic_energy(
+            self.handle, (ctypes.c_void_p * 3)(*[x.data_ptr() for x in u]), float(rho),
+            float(g_scale) if g_scale is not None else 0.0,
+            ctypes.byref(J) if want_J else None,
+            (ctypes.c_void_p * 3)(*[x.data_ptr() for x in seed]) if seed else None, _stream())
+        _check(st, "bcm_kinetic_energy", allow_warning=False)
+        return (J.value if want_J else None), seed
 
     def poisson_solve(self, b, p=None, use_guess=False, history=4096):
         """Solve A p = b (FP64 fields); returns (p, report)."""

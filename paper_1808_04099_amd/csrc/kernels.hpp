@@ -15,7 +15,7 @@ __host__ __device__ constexpr int face_stride(int NL) { return 6 * NL * NL + 6 *
 
 // Device-resident scalars of one Krylov solve (written by k_finalize, read by the kernels).
 struct Scalars {
-  double rr, rr0, bb, zr, zq, pq, alpha, beta, gU, spare[7];
+  double rr, rr0, bb, zr, zq, pq, alpha, beta, gU, vuu, spare[6];
 };
 
 // Host-visible copy of the scalars (pinned, coherent host memory): k_finalize writes the
@@ -129,7 +129,7 @@ struct FinalizeArgs {
   ScalarMirror* mirror;  // nullptr: none
   uint32_t seq;          // written to mirror->seq after the scalars
 };
-enum { OP_BB = 0, OP_RR0 = 1, OP_ZRZQ = 2, OP_PQ = 3, OP_RR = 4, OP_GU = 5 };
+enum { OP_BB = 0, OP_RR0 = 1, OP_ZRZQ = 2, OP_PQ = 3, OP_RR = 4, OP_GU = 5, OP_VUU = 6 };
 
 template <typename T>
 struct CoarseArgs {
@@ -199,7 +199,18 @@ struct AdjRhsArgs {     // g_u* = g_u_new + (1/c) W^T D^T lambda; forcing transp
   double inv_c;
   TF* gu[3];
   TF* galpha;
+  int accumulate;       // galpha += instead of =
   double* part_gU;
+};
+
+template <typename TF>
+struct KineticArgs {    // sum_i V_i |u_i|^2 (partials per workgroup); g_u = gscale V u
+  const CubeMeta* meta;
+  int n_cubes, n3;
+  const TF* u[3];
+  TF* gu[3];            // nullptr: no seed
+  double gscale;
+  double* part;         // nullptr: no sum
 };
 
 struct ScaleArgs {      // y = x * (vol ^ power) per cube (power = +1 or -1)
@@ -225,6 +236,7 @@ template <typename TF> hipError_t launch_correct(int NL, const CorrectArgs<TF>& 
 template <typename TF> hipError_t launch_adj_gp(int NL, const AdjGpArgs<TF>& a, hipStream_t s);
 template <typename TF> hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a, hipStream_t s);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
+template <typename TF> hipError_t launch_kinetic(const KineticArgs<TF>& a, int grid, hipStream_t s);
 template <typename T> hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s);
 // Multi-workgroup steps on one large graph level; n = lanes (cubes, nodes of the range, nodes
 // of the level for G_RESID, or nodes of the coarser level for G_RESTRICT).

@@ -314,11 +314,39 @@ __global__ __launch_bounds__(256) void k_adj_rhs(AdjRhsArgs<TF> a) {
       if (co == 0 && m.kind[2 * d] == FK_INFLOW) gU -= a.inv_c * lam / m.h;
       if (co == NL - 1 && m.kind[2 * d + 1] == FK_INFLOW) gU -= a.inv_c * lam / m.h;
     }
-    if (a.alpha && a.galpha) a.galpha[g] = TF(ga);
+    if (a.alpha && a.galpha) a.galpha[g] = a.accumulate ? TF(double(a.galpha[g]) + ga) : TF(ga);
   }
   if (a.part_gU) {
     const double t = block_sum(gU, red);
     if (threadIdx.x == 0) a.part_gU[blockIdx.x] = t;
+  }
+}
+
+// Kinetic-energy objective: per workgroup the FP64 sum of V_i |u_i|^2 over its cubes (V_i = h^3,
+// h the cube's cell width), and the seed cotangent gscale V_i u_i.  Workgroup w takes cubes
+// w, w + G, ... in index order, so the partials and their sum are reproducible.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_kinetic(KineticArgs<TF> a) {
+  __shared__ double red[8];
+  double acc = 0.0;
+  for (int c = blockIdx.x; c < a.n_cubes; c += gridDim.x) {
+    const double h = a.meta[c].h;
+    const double V = h * h * h;
+    for (int e = threadIdx.x; e < a.n3; e += 256) {
+      const size_t g = (size_t)c * a.n3 + e;
+      double uu = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double v = double(a.u[d][g]);
+        uu += v * v;
+        if (a.gu[d]) a.gu[d][g] = TF(a.gscale * V * v);
+      }
+      acc += V * uu;
+    }
+  }
+  if (a.part) {
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = t;
   }
 }
 
@@ -367,12 +395,19 @@ hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename TF>
+hipError_t launch_kinetic(const KineticArgs<TF>& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_kinetic<TF>), dim3(grid), dim3(WG), 0, s, a);
+  return hipGetLastError();
+}
+
 #define BCM_INST_F(TF)                                                                \
   template hipError_t launch_force<TF>(int, const ForceArgs<TF>&, hipStream_t);       \
   template hipError_t launch_div<TF>(int, const DivArgs<TF>&, hipStream_t);           \
   template hipError_t launch_correct<TF>(int, const CorrectArgs<TF>&, hipStream_t);   \
   template hipError_t launch_adj_gp<TF>(int, const AdjGpArgs<TF>&, hipStream_t);      \
-  template hipError_t launch_adj_rhs<TF>(int, const AdjRhsArgs<TF>&, hipStream_t);
+  template hipError_t launch_adj_rhs<TF>(int, const AdjRhsArgs<TF>&, hipStream_t);    \
+  template hipError_t launch_kinetic<TF>(const KineticArgs<TF>&, int, hipStream_t);
 BCM_INST_F(float)
 BCM_INST_F(double)
 

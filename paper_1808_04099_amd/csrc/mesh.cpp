@@ -5,6 +5,7 @@
 // equal cell counts and a neighbour adjacency table; cubes are visited along a Z-order
 // space-filling curve (Sec. 6.1) so that neighbouring cubes run close together in time.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -35,6 +36,78 @@ uint64_t spread3(uint64_t v) {
   uint64_t r = 0;
   for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (3 * b);
   return r;
+}
+
+// Geometry behind the boundary faces: a face whose four neighbour slots are empty must lie on
+// the domain boundary, i.e. no cube of any level may touch it from the outside (otherwise the
+// solver would apply a boundary rule where the geometry has a neighbour).  Cubes are hashed by
+// (level, integer position on the lattice of their level), anchored at the minimum corner of
+// the coarsest level present; every cube must sit on its level's lattice.  For each boundary
+// face the lookups are: the same-level cube across it, every coarser cube that would contain
+// the cell just across it, and the four cubes one level finer that would cover it (a mesh that
+// passed the link checks has no face neighbours two or more levels apart).
+bool check_boundary_faces(const HostMesh& M) {
+  const int nc = M.n_cubes;
+  if (nc == 0) return true;
+  int lmin = 127, lmax = 0;
+  for (int c = 0; c < nc; ++c) {
+    lmin = std::min<int>(lmin, M.level[c]);
+    lmax = std::max<int>(lmax, M.level[c]);
+  }
+  double anchor[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL};
+  for (int c = 0; c < nc; ++c)
+    if (M.level[c] == lmin)
+      for (int d = 0; d < 3; ++d) anchor[d] = std::min(anchor[d], M.origin[3 * c + d]);
+  using Key = std::array<int64_t, 4>;  // level, x, y, z
+  std::vector<Key> keys(nc);
+  std::vector<int64_t> pos(3 * size_t(nc));
+  for (int c = 0; c < nc; ++c) {
+    const double e = M.root_edge / std::ldexp(1.0, M.level[c]);
+    for (int d = 0; d < 3; ++d) {
+      const double off = (M.origin[3 * c + d] - anchor[d]) / e;
+      const double r = std::round(off);
+      if (std::fabs(off - r) > 1e-6 || std::fabs(r) > 1e15)
+        return fail("cube %d: base corner is not on the lattice of its level (axis %d)%s", c, d);
+      pos[3 * size_t(c) + d] = int64_t(r);
+    }
+    keys[c] = Key{M.level[c], pos[3 * size_t(c)], pos[3 * size_t(c) + 1], pos[3 * size_t(c) + 2]};
+  }
+  std::vector<Key> sorted(keys);
+  std::sort(sorted.begin(), sorted.end());
+  for (size_t i = 1; i < sorted.size(); ++i)
+    if (sorted[i] == sorted[i - 1]) {
+      const int c = int(std::find(keys.begin(), keys.end(), sorted[i]) - keys.begin());
+      return fail("cube %d: another cube of the same level has the same position%.0d%s", c, 0);
+    }
+  auto exists = [&](int lv, int64_t x, int64_t y, int64_t z) {
+    if (lv < lmin || lv > lmax) return false;
+    return std::binary_search(sorted.begin(), sorted.end(), Key{lv, x, y, z});
+  };
+  for (int c = 0; c < nc; ++c) {
+    const int lv = M.level[c];
+    const int64_t* p = &pos[3 * size_t(c)];
+    for (int f = 0; f < 6; ++f) {
+      const int* s = &M.nbr[(size_t(c) * 6 + f) * 4];
+      if (s[0] >= 0 || s[1] >= 0 || s[2] >= 0 || s[3] >= 0) continue;
+      const int d = f >> 1, side = f & 1;
+      int64_t q[3] = {p[0], p[1], p[2]};
+      q[d] += side ? 1 : -1;  // same-level position across the face
+      bool hit = exists(lv, q[0], q[1], q[2]);
+      for (int L = lv - 1; L >= lmin && !hit; --L) {  // coarser cubes containing that cell
+        const int sh = lv - L;
+        hit = exists(L, q[0] >> sh, q[1] >> sh, q[2] >> sh);
+      }
+      for (int w = 0; w < 4 && !hit; ++w) {  // one level finer: the four cubes covering the face
+        int64_t r[3] = {2 * p[0], 2 * p[1], 2 * p[2]};
+        r[d] += side ? 2 : -1;
+        r[tangential(d, 0)] += w & 1;
+        r[tangential(d, 1)] += w >> 1;
+        hit = exists(lv + 1, r[0], r[1], r[2]);
+      }
+      if (hit) return fail("cube %d face %d: marked as a domain boundary, but a cube lies across it%s", c, f);
+    }
+  }
+  return true;
 }
 
 bool validate(HostMesh& M) {
@@ -125,7 +198,7 @@ bool validate(HostMesh& M) {
     g_last_error = "mesh has no BCM_BC_OUTFLOW face: the Poisson problem would be singular";
     return false;
   }
-  return true;
+  return check_boundary_faces(M);
 }
 
 void derive(HostMesh& M) {
@@ -282,6 +355,7 @@ const char* bcm_status_string(int s) {
   switch (s) {
     case BCM_OK: return "BCM_OK";
     case BCM_NOT_CONVERGED: return "BCM_NOT_CONVERGED";
+    case BCM_STAGNATED: return "BCM_STAGNATED";
     case BCM_ERR_INVALID_ARG: return "BCM_ERR_INVALID_ARG";
     case BCM_ERR_INVALID_MESH: return "BCM_ERR_INVALID_MESH";
     case BCM_ERR_WORKSPACE: return "BCM_ERR_WORKSPACE";

@@ -324,10 +324,14 @@ int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s, Hook&& before_coarse) {
 struct SolveLog {
   bcm_report* rep;
   int iters = 0;
+  bool stalled = false;  // a Krylov solve stopped because its residual stopped decreasing
   void push(double v) {
     if (rep && rep->history && rep->history_len < rep->history_cap) rep->history[rep->history_len++] = v;
   }
 };
+
+constexpr int kStallChecks = 10;      // checks without progress that count as stagnation
+constexpr double kStallFactor = 0.99;  // progress = the residual norm falls below 0.99 x best
 
 // Flexible CG (or plain V-cycle iteration) on A x = r0 with r (= P->o_r) holding the initial
 // residual and x the accumulator (x_zero: x starts at zero and is not read before its first
@@ -388,6 +392,10 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     if (!e) e = start_x(false, nullptr);  // nothing left to run beside: on the caller's stream
     return st ? st : e;
   };
+  // stagnation: kStallChecks convergence checks in a row without a 1% reduction of the best
+  // residual norm seen so far end the solve early (the iterate stays valid)
+  double best_rr = HUGE_VAL;
+  int stall = 0;
   for (int it = 0; it < max_iter; ++it) {
     int st = vcycle<T>(P, (flex && it > 0) ? q : nullptr, s,
                        [&](CoarseMGArgs<T>* carrier) { return start_x(true, carrier); });
@@ -420,6 +428,13 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     }
     log.push(std::sqrt(std::max(hs->rr, 0.0)) * hist_scale);
     if (hs->rr <= thr) break;
+    if (hs->rr < kStallFactor * kStallFactor * best_rr) {
+      best_rr = hs->rr;
+      stall = 0;
+    } else if (++stall >= kStallChecks) {
+      log.stalled = true;
+      break;
+    }
   }
   return finish(BCM_OK);
 }
@@ -440,7 +455,13 @@ int residual64(bcm_plan* P, const double* p, const double* b, TO* r, double rsca
   return finalize(P, OP_BB, 0, 1, partials_of(NL, P->nc), 0, s);
 }
 
+constexpr double kFp64Floor = 64 * 2.220446049250313e-16;  // relative residual FP64 can reach
+
 // Solve A p = b to opts.tol (relative, V-weighted, FP64).  p holds the guess if use_guess.
+// Every return path reports the true FP64 residual of the returned p: a pass that updated p
+// after the last residual evaluation (the limits were reached) is followed by one more
+// evaluation.  The solve stops early with BCM_STAGNATED when a whole FP64 Krylov pass fails to
+// halve the true residual norm, or two refinement steps in a row fail to (mixed).
 int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report* rep, hipStream_t s) {
   const bcm_solver_opts& o = P->o;
   SolveLog log{rep};
@@ -452,19 +473,23 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
   if (!use_guess) HIPCHK(fill<double>(p, P->cells, s), "zero fill");
   double bb = 0.0, rr = 0.0;
   const double tol2 = o.tol * o.tol;
-  bool converged = false;
+  bool converged = false, stagnated = false;
+  bool unchecked = false;  // p changed since rr was evaluated
+  auto nonfinite = [&]() {
+    set_error("non-finite right-hand side or residual");
+    return BCM_ERR_NONFINITE;
+  };
   if (!P->inner32) {
     // FP64: flexible CG directly on p, restarted from the true residual if the recurrence
     // residual and the true one disagree at the end.
+    double rr_prev = HUGE_VAL;
     for (outer = 0; outer < std::max(1, o.max_outer); ++outer) {
       if ((st = residual64<double>(P, p, b, P->at<double>(P->o_r), 1.0, s))) return st;
       if ((st = read_scalars(P, &hs, s))) return st;
+      unchecked = false;
       bb = hs.bb;
       rr = hs.rr;
-      if (!std::isfinite(rr) || !std::isfinite(bb)) {
-        set_error("non-finite right-hand side or residual");
-        return BCM_ERR_NONFINITE;
-      }
+      if (!std::isfinite(rr) || !std::isfinite(bb)) return nonfinite();
       if (bb == 0.0) {
         HIPCHK(fill<double>(p, P->cells, s), "zero fill");
         rr = 0.0;
@@ -476,28 +501,43 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
         converged = true;
         break;
       }
+      if (outer > 0 && rr > 0.25 * rr_prev) {  // a whole Krylov pass did not halve it
+        stagnated = true;
+        break;
+      }
+      rr_prev = rr;
       if (log.iters >= o.max_iter) break;
-      if ((st = krylov<double>(P, p, false, tol2 * bb * 0.25, o.max_iter - log.iters, 1.0 / std::sqrt(bb),
-                               log, &hs, s)))
+      // the recurrence residual is not asked to go below what FP64 can resolve: a tolerance
+      // under that floor ends in a restart whose true residual shows the stagnation
+      const double thr = std::max(tol2 * 0.25, kFp64Floor * kFp64Floor) * bb;
+      if ((st = krylov<double>(P, p, false, thr, o.max_iter - log.iters, 1.0 / std::sqrt(bb), log, &hs, s)))
         return st;
+      unchecked = true;
+    }
+    if (unchecked) {  // the last restart's update has not been evaluated yet
+      if ((st = residual64<double>(P, p, b, P->at<double>(P->o_r), 1.0, s))) return st;
+      if ((st = read_scalars(P, &hs, s))) return st;
+      rr = hs.rr;
+      if (!std::isfinite(rr)) return nonfinite();
+      log.push(std::sqrt(rr / bb));
+      converged = rr <= tol2 * bb;
     }
   } else {
     // Mixed: FP64 residual and update, FP32 inner flexible CG.  The residual handed to the
     // inner solve is scaled to unit RMS (by the predicted norm) so FP32 range never matters.
     const double vol = double(P->cells);
-    double rscale = 1.0;
+    double rscale = 1.0, rr_prev = HUGE_VAL;
+    int slow = 0;  // consecutive refinement steps that did not halve the residual norm
     for (outer = 0; outer < o.max_outer; ++outer) {
       float* r32 = P->at<float>(P->o_r);
       const double* pg = (use_guess || outer) ? p : nullptr;
       if ((st = residual64<float>(P, pg, b, r32, rscale, s, faces_ok))) return st;
       faces_ok = pg != nullptr;
       if ((st = read_scalars(P, &hs, s))) return st;
+      unchecked = false;
       if (outer == 0) bb = hs.bb;
       rr = hs.rr;
-      if (!std::isfinite(rr) || !std::isfinite(bb)) {
-        set_error("non-finite right-hand side or residual");
-        return BCM_ERR_NONFINITE;
-      }
+      if (!std::isfinite(rr) || !std::isfinite(bb)) return nonfinite();
       if (bb == 0.0) {
         HIPCHK(fill<double>(p, P->cells, s), "zero fill");
         faces_ok = false;
@@ -510,6 +550,12 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
         converged = true;
         break;
       }
+      slow = rr > 0.25 * rr_prev ? slow + 1 : 0;
+      if (slow >= 2) {
+        stagnated = true;
+        break;
+      }
+      rr_prev = rr;
       if (outer == 0 && !(rscale > 0 && std::fabs(std::log10(rr / vol)) < 20)) {
         // first pass unscaled and far from unit size: redo the conversion with the true norm
         rscale = 1.0 / std::sqrt(rr / vol);
@@ -526,19 +572,29 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
       IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale};
       HIPCHK(timed(P, cls_of("ir", 0), s, [&] { return launch_ir<float>(P->n, ia, s); }), "kc_ir");
       faces_ok = true;  // kc_ir exports the faces of the updated p
+      unchecked = true;
       const double rr_est = hs.rr / (rscale * rscale);
       if (rr_est > 0 && std::isfinite(rr_est)) rscale = 1.0 / std::sqrt(rr_est / vol);
     }
+    if (unchecked) {  // the last refinement step has not been evaluated yet
+      if ((st = residual64<float>(P, p, b, P->at<float>(P->o_r), rscale, s, faces_ok))) return st;
+      if ((st = read_scalars(P, &hs, s))) return st;
+      rr = hs.rr;
+      if (!std::isfinite(rr)) return nonfinite();
+      log.push(std::sqrt(rr / bb));
+      converged = rr <= tol2 * bb;
+    }
   }
+  const int status = converged ? BCM_OK : stagnated ? BCM_STAGNATED : BCM_NOT_CONVERGED;
   if (rep) {
-    rep->n_outer = outer + (converged ? 0 : 0);
+    rep->n_outer = outer;
     rep->n_inner = log.iters;
     rep->final_rel_res = bb > 0 ? std::sqrt(std::max(rr, 0.0) / bb) : 0.0;
-    rep->status = converged ? BCM_OK : BCM_NOT_CONVERGED;
+    rep->status = status;
   }
   // leave the faces of p exported for the correction kernels
   if (!faces_ok && (st = export64(P, p, P->at<double>(P->o_pf), s))) return st;
-  return converged ? BCM_OK : BCM_NOT_CONVERGED;
+  return status;
 }
 
 // Forcing -> right-hand side -> Poisson -> correction (or, with p_given, forcing and
@@ -641,16 +697,45 @@ int adjoint_impl(bcm_plan* P, const bcm_adjoint_in* in, bcm_adjoint_out* out, bc
     ra.gu[d] = static_cast<TF*>(out->g_u[d]);
   }
   ra.galpha = static_cast<TF*>(out->g_alpha);
+  ra.accumulate = out->accumulate != 0;
   ra.inv_c = 1.0 / c;
   ra.part_gU = P->at<double>(P->o_part[0]);
   HIPCHK(timed(P, cls_of("adj_rhs", 0), s, [&] { return launch_adj_rhs<TF>(NL, ra, s); }), "k_adj_rhs");
   if ((e = finalize(P, OP_GU, 0, -1, n_wg(NL, P->nc), 0, s))) return e;
   Scalars hs{};
   if ((e = read_scalars(P, &hs, s))) return e;
-  out->g_U_in = hs.gU;
+  out->g_U_in = (out->accumulate ? out->g_U_in : 0.0) + hs.gU;
   if (out->lambda)
     HIPCHK(hipMemcpyAsync(out->lambda, lam, P->cells * sizeof(double), hipMemcpyDeviceToDevice, s), "copy lambda");
   return st;
+}
+
+// J = (rho/2) sum_i V_i |u_i|^2 and the seed cotangent g_scale rho V_i u_i.
+template <typename TF>
+int kinetic_impl(bcm_plan* P, const void* const u[3], double rho, double g_scale, double* J,
+                 void* const g_u[3], hipStream_t s) {
+  KineticArgs<TF> ka{};
+  ka.meta = P->at<const CubeMeta>(P->o_meta);
+  ka.n_cubes = P->nc;
+  ka.n3 = P->n * P->n * P->n;
+  for (int d = 0; d < 3; ++d) {
+    ka.u[d] = static_cast<const TF*>(u[d]);
+    ka.gu[d] = g_u ? static_cast<TF*>(g_u[d]) : nullptr;
+  }
+  ka.gscale = g_scale * rho;
+  const int grid = std::min(P->nc, 2048);  // the partial buffers hold >= n_cubes values
+  ka.part = J ? P->at<double>(P->o_part[0]) : nullptr;
+  HIPCHK(launch_kinetic<TF>(ka, grid, s), "k_kinetic");
+  if (!J) return BCM_OK;
+  if (int e = finalize(P, OP_VUU, 0, -1, grid, 0, s)) return e;
+  Scalars hs{};
+  if (int e = read_scalars(P, &hs, s)) return e;
+  if (!std::isfinite(hs.vuu)) {
+    set_error("bcm_kinetic_energy: non-finite velocity");
+    return BCM_ERR_NONFINITE;
+  }
+  *J = 0.5 * rho * hs.vuu;
+  return BCM_OK;
 }
 
 // Upload the cube-graph hierarchy (converted to the inner precision T) and its level table.
@@ -1000,6 +1085,20 @@ int bcm_project_adjoint(bcm_plan* P, const bcm_adjoint_in* in, bcm_adjoint_out* 
   st = P->fields32 ? adjoint_impl<float>(P, in, out, rep, s) : adjoint_impl<double>(P, in, out, rep, s);
   if (rep) rep->status = st;
   return st;
+}
+
+int bcm_kinetic_energy(bcm_plan* P, const void* const u[3], double rho, double g_scale, double* J,
+                       void* const g_u[3], void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!u || !u[0] || !u[1] || !u[2] || !(rho > 0) || !std::isfinite(g_scale) ||
+      (g_u && (!g_u[0] || !g_u[1] || !g_u[2]))) {
+    set_error("bcm_kinetic_energy: NULL field, non-positive rho or non-finite g_scale");
+    return BCM_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return P->fields32 ? kinetic_impl<float>(P, u, rho, g_scale, J, g_u, s)
+                     : kinetic_impl<double>(P, u, rho, g_scale, J, g_u, s);
 }
 
 int bcm_poisson_solve(bcm_plan* P, const double* d_b, double* d_p, int use_guess, bcm_report* rep,

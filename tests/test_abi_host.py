@@ -162,3 +162,32 @@ def test_status_strings_and_timer_names():
     from paper_1808_04099_amd import timing_names
     names = timing_names()
     assert "postsmooth16" in names and "coarse" in names
+
+
+@pytest.mark.parametrize("which", ["uniform", "multilevel"])
+def test_boundary_face_with_a_cube_across_is_rejected(which):
+    """A face whose neighbour slots are empty must lie on the domain boundary: unlinking two
+    touching cubes and marking both faces as open boundaries is caught by the geometry check."""
+    m = (uniform_mesh((3, 2, 2), 0.25, 4, CHANNEL_BC) if which == "uniform"
+         else configs.multilevel_small()["mesh"])
+    nbr, bc = m.nbr.copy(), m.face_bc.copy()
+    if which == "uniform":
+        c, f = 0, 1
+    else:                                  # a coarse face with four finer neighbours
+        c, f = map(int, np.argwhere(nbr[:, :, 1] >= 0)[0])
+    others = [int(o) for o in nbr[c, f] if o >= 0]
+    nbr[c, f] = -1
+    bc[c, f] = 1
+    for o in others:
+        nbr[o, f ^ 1] = -1
+        bc[o, f ^ 1] = 1
+    st, msg = _create(m, nbr=nbr, face_bc=bc)
+    assert st == -2 and "a cube lies across it" in msg, msg
+
+
+def test_overlapping_cubes_are_rejected():
+    m = uniform_mesh((3, 2, 2), 0.25, 4, CHANNEL_BC)
+    origin = m.origin.copy()
+    origin[1] = origin[0] + 0.1            # off the level lattice
+    st, msg = _create(m, origin=origin)
+    assert st == -2, msg

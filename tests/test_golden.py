@@ -56,7 +56,7 @@ def test_gpu_matches_tiny_channel_golden():
     ul = MultiStepProjection.apply(nz[0] + U, nz[1], nz[2], a_t, U, plan, prm["dt"], prm["rho"],
                                    prm["steps"])
     vol = dev(np.repeat(m.h() ** 3, m.n ** 3))
-    J = kinetic_energy(ul, vol, prm["rho"])
+    J = kinetic_energy(ul, plan, prm["rho"])
     J.backward()
     assert abs(J.item() - g["J"]) <= 1e-10 * abs(g["J"])
     assert np.allclose(host(a_t.grad)[SAMPLE], g["g_alpha"], rtol=1e-7,

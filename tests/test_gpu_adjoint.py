@@ -67,7 +67,7 @@ def _J(plan, pr, alpha_t, U, steps, vol, noise):
     u0 = [noise[0] + U, noise[1], noise[2]]
     u = MultiStepProjection.apply(u0[0], u0[1], u0[2], alpha_t, U, plan, pr["dt"], pr["rho"],
                                   steps)
-    return kinetic_energy(u, vol, pr["rho"])
+    return kinetic_energy(u, plan, pr["rho"])
 
 
 def test_multistep_gradient_matches_oracle_subcase():
@@ -126,3 +126,62 @@ def test_gradient_matches_central_differences(which):
         worst = max(worst, rel)
         log(f"  dir {k}: adjoint {adj:.12e} fd {fd:.12e} rel {rel:.2e}")
     assert worst <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_f32fields"])
+def test_kinetic_energy_and_seed_match_oracle(precision):
+    """bcm_kinetic_energy: J against the oracle's J = (rho/2) sum V |u|^2 on the three-level
+    mesh (FP32 fields: the oracle evaluates the FP32-rounded inputs), and the seed cotangent
+    g_scale rho V u cell by cell."""
+    pr = configs.multilevel_small()
+    m = pr["mesh"]
+    plan = plan_for(m, precision)
+    f32 = precision == "mixed_f32fields"
+    u = uniform_random_velocity(m, 51, 0.7, (0.9, -0.2, 0.1)).reshape(3, -1)
+    if f32:
+        u = u.astype(np.float32).astype(np.float64)
+    rho, gs = 1.3, -0.75
+    J_ref = OP.kinetic_energy(FVMesh(m), u, rho)
+    ut = [dev(u[d], plan.field_dtype) for d in range(3)]
+    J, seed = plan.kinetic_energy(ut, rho, g_scale=gs)
+    V = np.repeat(m.h() ** 3, m.n ** 3)
+    log(f"  J gpu={J:.15e} oracle={J_ref:.15e}")
+    assert abs(J - J_ref) <= 1e-13 * J_ref
+    tol = 1e-7 if f32 else 1e-15
+    for d in range(3):
+        ref = gs * rho * V * u[d]
+        assert np.abs(host(seed[d]) - ref).max() <= tol * np.abs(ref).max()
+    # J only, no seed; and the seed only, without a readback
+    J2, none = plan.kinetic_energy(ut, rho)
+    assert none is None and J2 == J
+    J3, seed3 = plan.kinetic_energy(ut, rho, g_scale=gs, want_J=False)
+    assert J3 is None and all(torch.equal(seed3[d], seed[d]) for d in range(3))
+
+
+def test_backward_recomputes_each_step_once():
+    """The reverse sweep of K steps runs K - 1 recomputations (forcing + correction): the
+    'correct' kernel class is launched K - 1 times during the backward."""
+    from paper_1808_04099_amd import MultiStepProjection, kinetic_energy
+    pr = configs.adjoint_subcase(n=8)
+    m = pr["mesh"]
+    K = pr["steps"]
+    plan = plan_for(m, "fp64", tol=1e-12)
+    noise = [dev(pr["noise"][d]) for d in range(3)]
+    a_t = dev(pr["alpha"]).requires_grad_(True)
+    U = torch.tensor(pr["U_in"], dtype=torch.float64, requires_grad=True)
+    u = MultiStepProjection.apply(noise[0] + U, noise[1], noise[2], a_t, U, plan, pr["dt"],
+                                  pr["rho"], K)
+    J = kinetic_energy(u, plan, pr["rho"])
+    plan.timing_enable("correct")
+    J.backward()
+    n, _ = plan.timing_read()
+    plan.timing_enable(None)
+    log(f"  K={K}: {n} correction launches in the backward")
+    assert n == K - 1
+    fv = FVMesh(m)
+    J_ref, ga_ref, gU_ref = OP.multistep_gradient(fv, pr["noise"].reshape(3, -1),
+                                                  pr["alpha"].ravel(), (0, 0, 0), pr["U_in"],
+                                                  pr["dt"], pr["rho"], K)
+    assert abs(J.item() - J_ref) <= 1e-9 * abs(J_ref)
+    assert rel_err(host(a_t.grad), ga_ref) <= 1e-7
+    assert abs(U.grad.item() - gU_ref) <= 1e-7 * abs(gU_ref)

@@ -114,7 +114,7 @@ def test_multilevel_multistep_gradient_matches_oracle(precision):
     U = torch.tensor(pr["U_in"], dtype=torch.float64, requires_grad=True)
     u0 = [nz[0] + U.to(ft), nz[1], nz[2]]
     u = MultiStepProjection.apply(u0[0], u0[1], u0[2], a_t, U, plan, pr["dt"], pr["rho"], steps)
-    J = kinetic_energy(u, vol, pr["rho"])
+    J = kinetic_energy(u, plan, pr["rho"])
     J.backward()
     tol = 1e-4 if f32 else 1e-7
     log(f"  J gpu={J.item():.12e} oracle={J_ref:.12e}; dJ/dU gpu={U.grad.item():.10e} "
