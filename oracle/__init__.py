@@ -12,6 +12,8 @@ never does, and shares no code with it.
                  kinetic-energy objective, its gradient and a complex-step directional derivative
   sample.py      stencil rows evaluated at individually chosen cells (for meshes too large to
                  assemble)
+  momentum.py    the momentum sub-step (QUICK convection, diffusion; Euler, AB2, Crank-Nicolson)
+                 on single-level meshes, array form with two-layer ghost cells
   composite.py   the Laplacian, divergence and residual norm of any mesh as whole-array
                  expressions over the cube-major fields (full-size residuals of the 3-level mesh)
 
