@@ -198,6 +198,39 @@ typedef struct {
                             objective sums them over the steps) */
 } bcm_adjoint_out;
 
+/* Momentum sub-step schemes (Sec. 3: the paper's code offers Euler, Adams-Bashforth and
+ * Crank-Nicolson). */
+enum {
+  BCM_EULER = 0,  /* u~ = u^n + dt H(u^n) */
+  BCM_AB2 = 1,    /* u~ = u^n + dt (3/2 H(u^n) - 1/2 H(u^{n-1})); Euler when h_prev is NULL */
+  BCM_CN = 2      /* u~ = u^n + dt/2 (H(u~) + H(u^n)), the advecting velocity frozen at u^n */
+};
+
+/* Inputs of the momentum sub-step (Sec. 3, Eq. (substep1)): the intermediate velocity u~ from
+ * u^n without body force and pressure, H(v) = -A[v] + nu D[v] with A the QUICK convection in
+ * finite-volume flux form (face velocities of u^n: mean of the two cells, as in the projection
+ * step) and D the 7-point diffusion; velocity boundary values by two mirrored ghost layers per
+ * domain face (inflow: every component fixed, the normal one U_in into the domain; slip: the
+ * normal component 0, the tangential ones zero gradient; open: zero gradient). */
+typedef struct {
+  const void* u[3];       /* u^n (device fields of the field type) */
+  const void* h_prev[3];  /* BCM_AB2: H(u^{n-1}) of the previous step (three fields), or all
+                             NULL on the first step; ignored by the other schemes */
+  double U_in;            /* inflow speed on BCM_BC_INFLOW faces */
+  double dt;              /* time step (> 0) */
+  double nu;              /* kinematic viscosity mu / rho (>= 0) */
+  int32_t scheme;         /* BCM_EULER / BCM_AB2 / BCM_CN */
+  double cn_tol;          /* BCM_CN: Jacobi iterations run until ||r||_2 <= cn_tol ||rhs||_2
+                             (r = rhs + dt/2 H(x) - x, rhs = u^n + dt/2 H(u^n); 2-norms over
+                             all cells and components); 0 = 1e-12 */
+  int32_t cn_max_iter;    /* BCM_CN: iteration limit; 0 = 200 */
+} bcm_momentum_in;
+
+typedef struct {
+  void* u_tilde[3];       /* intermediate velocity u~ (written; must not alias u) */
+  void* h[3];             /* optional: H(u^n) (the next AB2 step's h_prev), or all NULL */
+} bcm_momentum_out;
+
 /* Fill opts with the defaults listed in bcm_solver_opts. */
 void bcm_default_opts(bcm_solver_opts* opts);
 
@@ -237,6 +270,16 @@ int bcm_project_recompute(bcm_plan* plan, const bcm_project_in* in, const double
  * interpolation, divergence and forcing.  Solver options as for the forward call. */
 int bcm_project_adjoint(bcm_plan* plan, const bcm_adjoint_in* in, bcm_adjoint_out* out,
                         bcm_report* report, void* stream);
+
+/* Momentum sub-step (Sec. 3, Eq. (substep1)) on single-level meshes with n >= 4 (other meshes:
+ * BCM_ERR_UNSUPPORTED).  Explicit schemes are one pass; Crank-Nicolson iterates Jacobi sweeps
+ * on its linear system from the Euler predictor, with a convergence check every check_every
+ * iterations (solver options): report.n_inner = iterations, history = ||r|| / ||rhs|| at each
+ * check, final_rel_res = the last of them, which is the residual of the iterate that the last
+ * sweep started from (the returned iterate is one sweep further).  BCM_NOT_CONVERGED if cn_max_iter is reached first (output valid),
+ * BCM_ERR_NONFINITE if a norm is not finite.  report may be NULL. */
+int bcm_momentum(bcm_plan* plan, const bcm_momentum_in* in, bcm_momentum_out* out,
+                 bcm_report* report, void* stream);
 
 /* Objective of the differentiable multi-step projection: the kinetic energy of a cell-centred
  * velocity field, J = (rho/2) sum_i V_i |u_i|^2 with V_i = h_i^3 the cell volume (the paper

@@ -55,6 +55,18 @@ class AdjointOut(ctypes.Structure):
                 ("lambda_", c_void_p), ("accumulate", c_int32)]
 
 
+class MomentumIn(ctypes.Structure):
+    _fields_ = [("u", c_void_p * 3), ("h_prev", c_void_p * 3), ("U_in", c_double),
+                ("dt", c_double), ("nu", c_double), ("scheme", c_int32), ("cn_tol", c_double),
+                ("cn_max_iter", c_int32)]
+
+
+class MomentumOut(ctypes.Structure):
+    _fields_ = [("u_tilde", c_void_p * 3), ("h", c_void_p * 3)]
+
+
+SCHEMES = {"euler": 0, "ab2": 1, "cn": 2}
+
 EXPORTS = {
     "bcm_default_opts": (None, [POINTER(SolverOpts)]),
     "bcm_mesh_create": (c_int, [POINTER(MeshDesc), POINTER(c_void_p)]),
@@ -72,6 +84,8 @@ EXPORTS = {
     "bcm_poisson_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_int, POINTER(Report),
                                   c_void_p]),
     "bcm_apply_laplacian": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "bcm_momentum": (c_int, [c_void_p, POINTER(MomentumIn), POINTER(MomentumOut),
+                             POINTER(Report), c_void_p]),
     "bcm_kinetic_energy": (c_int, [c_void_p, POINTER(c_void_p), c_double, c_double,
                                    POINTER(c_double), POINTER(c_void_p), c_void_p]),
     "bcm_timing_enable": (c_int, [c_void_p, c_char_p]),

@@ -241,6 +241,28 @@ class Plan:
         _check(st, "bcm_project_adjoint")
         return g_u, g_alpha, float(aout.g_U_in), _unpack(rep, hist), lam
 
+    def momentum(self, u, U_in, dt, nu, scheme="cn", h_prev=None, want_h=False, cn_tol=0.0,
+                 cn_max_iter=0, out=None, history=4096):
+        """Momentum sub-step u^n -> u~ (scheme "euler", "ab2" or "cn"); returns dict(u_tilde=[3],
+        h=[3] = H(u^n) or None, report)."""
+        u = [self._field(x, f"u[{d}]") for d, x in enumerate(u)]
+        hp = [self._field(x, f"h_prev[{d}]") for d, x in enumerate(h_prev)] if h_prev else None
+        ut = out or [self.empty() for _ in range(3)]
+        h = [self.empty() for _ in range(3)] if want_h else None
+        mi = L.MomentumIn((ctypes.c_void_p * 3)(*[x.data_ptr() for x in u]),
+                          (ctypes.c_void_p * 3)(*([x.data_ptr() for x in hp] if hp else
+                                                  [None] * 3)),
+                          float(U_in), float(dt), float(nu), L.SCHEMES[scheme], float(cn_tol),
+                          int(cn_max_iter))
+        mo = L.MomentumOut((ctypes.c_void_p * 3)(*[x.data_ptr() for x in ut]),
+                           (ctypes.c_void_p * 3)(*([x.data_ptr() for x in h] if h else
+                                                   [None] * 3)))
+        rep, hist = _report(history)
+        st = self._lib.bcm_momentum(self.handle, ctypes.byref(mi), ctypes.byref(mo),
+                                    ctypes.byref(rep), _stream())
+        _check(st, "bcm_momentum")
+        return dict(u_tilde=ut, h=h, report=_unpack(rep, hist))
+
     def kinetic_energy(self, u, rho, g_scale=None, want_J=True):
         """J = (rho/2) sum_i V_i |u_i|^2 (host float, or None with want_J=False) and, when
         g_scale is given, the seed cotangent g_scale * rho * V * u (three fields; else None)."""

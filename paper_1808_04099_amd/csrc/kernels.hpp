@@ -129,7 +129,7 @@ struct FinalizeArgs {
   ScalarMirror* mirror;  // nullptr: none
   uint32_t seq;          // written to mirror->seq after the scalars
 };
-enum { OP_BB = 0, OP_RR0 = 1, OP_ZRZQ = 2, OP_PQ = 3, OP_RR = 4, OP_GU = 5, OP_VUU = 6 };
+enum { OP_BB = 0, OP_RR0 = 1, OP_ZRZQ = 2, OP_PQ = 3, OP_RR = 4, OP_GU = 5, OP_VUU = 6, OP_B0 = 7 };
 
 template <typename T>
 struct CoarseArgs {
@@ -213,6 +213,38 @@ struct KineticArgs {    // sum_i V_i |u_i|^2 (partials per workgroup); g_u = gsc
   double* part;         // nullptr: no sum
 };
 
+// Momentum sub-step (kernels_mom.hip).  Two-layer face buffers: 12 n^2 values per cube and
+// component.
+enum { MOM_EXPLICIT = 0, MOM_CN_START = 1, MOM_CN_ITER = 2 };
+
+template <typename TF>
+struct MomExportArgs {
+  int n_cubes;
+  const TF* x[3];
+  TF* xf[3];
+};
+
+template <typename TF>
+struct MomArgs {
+  // MOM_EXPLICIT  out = v + dt (c1 H(v) + c2 hprev)                 (v = a = u^n)
+  // MOM_CN_START  rhs = v + dt/2 H(v); out = v + dt H(v); part: sum rhs^2   (v = a = u^n)
+  // MOM_CN_ITER   r = rhs + dt/2 H(v) - v; out = v + r / diag; part: sum r^2 (v = iterate)
+  // every mode: hout = H(v) (optional), outf = two-layer faces of out (optional)
+  const CubeMeta* meta;
+  int n_cubes;
+  const TF* v[3];
+  const TF* vf[3];
+  const TF* a[3];
+  const TF* af[3];
+  const TF* hprev[3];
+  TF* rhs[3];
+  TF* out[3];
+  TF* outf[3];
+  TF* hout[3];
+  double U_in, nu, dt, c1, c2;
+  double* part;
+};
+
 struct ScaleArgs {      // y = x * (vol ^ power) per cube (power = +1 or -1)
   const CubeMeta* meta;
   int n_cubes, n3;
@@ -237,6 +269,8 @@ template <typename TF> hipError_t launch_adj_gp(int NL, const AdjGpArgs<TF>& a, 
 template <typename TF> hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a, hipStream_t s);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 template <typename TF> hipError_t launch_kinetic(const KineticArgs<TF>& a, int grid, hipStream_t s);
+template <typename TF> hipError_t launch_mom_export(int NL, const MomExportArgs<TF>& a, int grid, hipStream_t s);
+template <typename TF> hipError_t launch_mom(int NL, int mode, const MomArgs<TF>& a, int grid, hipStream_t s);
 template <typename T> hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s);
 // Multi-workgroup steps on one large graph level; n = lanes (cubes, nodes of the range, nodes
 // of the level for G_RESID, or nodes of the coarser level for G_RESTRICT).

@@ -118,6 +118,9 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalizeArgs a) {
     case OP_VUU:
       sc->vuu = t0;
       break;
+    case OP_B0:
+      sc->bb = t0;
+      break;
   }
   if (a.mirror) {
     a.mirror->sc = *sc;

@@ -44,7 +44,7 @@ const char* const kTimerNames[] = {"presmooth16", "presmooth8", "presmooth4", "p
                                    "restrict8", "restrict4", "restrict2", "apply16", "apply8",
                                    "apply4", "apply2", "update", "resid64", "ir", "coarse",
                                    "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
-                                   "export", "xupdate", nullptr};
+                                   "export", "xupdate", "momentum", nullptr};
 
 int level_index(int NL) { return NL == 16 ? 0 : NL == 8 ? 1 : NL == 4 ? 2 : 3; }
 
@@ -76,6 +76,11 @@ struct bcm_plan {
   // workspace offsets
   size_t o_meta = 0, o_launch = 0, o_part[3] = {0, 0, 0}, o_sc = 0, o_cw = 0;
   size_t o_nb27 = 0;  // 27-neighbourhoods (trilinear prolongation), 0 = not used
+  // momentum sub-step (single-level meshes with n >= 4, else 0): two-layer faces of u^n and of
+  // the two Crank-Nicolson iterates, its right-hand side and a second iterate
+  size_t o_mfa[3] = {0, 0, 0}, o_mfv[2][3] = {{0, 0, 0}, {0, 0, 0}}, o_mrhs[3] = {0, 0, 0},
+         o_mit[3] = {0, 0, 0};
+  bool momentum = false;
   size_t o_ustar[3] = {0, 0, 0}, o_uf = 0, o_b64 = 0, o_pf = 0, o_lam = 0;
   size_t o_r = 0, o_z = 0, o_p = 0, o_q = 0, o_d = 0;
   size_t o_zf[2] = {0, 0}, o_pfk[2] = {0, 0};
@@ -738,6 +743,117 @@ int kinetic_impl(bcm_plan* P, const void* const u[3], double rho, double g_scale
   return BCM_OK;
 }
 
+// Momentum sub-step (Eq. (substep1)): export the two-layer faces of u^n, then one explicit pass
+// (Euler, AB2) or the Crank-Nicolson start and its Jacobi iterations, which alternate between
+// the caller's output and the plan's second iterate.
+template <typename TF>
+int momentum_impl(bcm_plan* P, const bcm_momentum_in* in, bcm_momentum_out* out, bcm_report* rep,
+                  hipStream_t s) {
+  const int NL = P->n, nc = P->nc;
+  const int units = nc;  // cubes or groups of cubes; the grid never exceeds the partial buffers
+  const int grid = std::min(units, 2048);
+  MomExportArgs<TF> ea{};
+  ea.n_cubes = nc;
+  for (int d = 0; d < 3; ++d) {
+    ea.x[d] = static_cast<const TF*>(in->u[d]);
+    ea.xf[d] = P->at<TF>(P->o_mfa[d]);
+  }
+  HIPCHK(timed(P, cls_of("momentum", 0), s, [&] { return launch_mom_export<TF>(NL, ea, grid, s); }),
+         "k_mom_export");
+  MomArgs<TF> ma{};
+  ma.meta = P->at<const CubeMeta>(P->o_meta);
+  ma.n_cubes = nc;
+  for (int d = 0; d < 3; ++d) {
+    ma.v[d] = static_cast<const TF*>(in->u[d]);
+    ma.vf[d] = P->at<const TF>(P->o_mfa[d]);
+    ma.a[d] = static_cast<const TF*>(in->u[d]);
+    ma.af[d] = P->at<const TF>(P->o_mfa[d]);
+    ma.hprev[d] = static_cast<const TF*>(in->h_prev[d]);
+    ma.rhs[d] = P->at<TF>(P->o_mrhs[d]);
+    ma.out[d] = static_cast<TF*>(out->u_tilde[d]);
+    ma.hout[d] = static_cast<TF*>(out->h[d]);
+  }
+  ma.U_in = in->U_in;
+  ma.nu = in->nu;
+  ma.dt = in->dt;
+  SolveLog log{rep};
+  if (rep) rep->history_len = 0;
+  auto launch = [&](int mode) {
+    return timed(P, cls_of("momentum", 0), s, [&] { return launch_mom<TF>(NL, mode, ma, grid, s); });
+  };
+  if (in->scheme != BCM_CN) {
+    const bool ab2 = in->scheme == BCM_AB2 && in->h_prev[0];
+    ma.c1 = ab2 ? 1.5 : 1.0;
+    ma.c2 = ab2 ? -0.5 : 0.0;
+    if (!ab2)
+      for (int d = 0; d < 3; ++d) ma.hprev[d] = nullptr;
+    HIPCHK(launch(MOM_EXPLICIT), "k_mom (explicit)");
+    if (rep) {
+      rep->status = BCM_OK;
+      rep->n_outer = 0;
+      rep->n_inner = 0;
+      rep->final_rel_res = 0.0;
+    }
+    return BCM_OK;
+  }
+  const double tol = in->cn_tol > 0 ? in->cn_tol : 1e-12;
+  const int max_iter = in->cn_max_iter > 0 ? in->cn_max_iter : 200;
+  // start: rhs = u^n + dt/2 H(u^n), first iterate (Euler predictor) into the caller's output
+  for (int d = 0; d < 3; ++d) ma.outf[d] = P->at<TF>(P->o_mfv[0][d]);
+  ma.part = P->at<double>(P->o_part[0]);
+  HIPCHK(launch(MOM_CN_START), "k_mom (Crank-Nicolson start)");
+  if (int e = finalize(P, OP_B0, 0, -1, grid, 0, s)) return e;
+  for (int d = 0; d < 3; ++d) ma.hout[d] = nullptr;
+  TF* bufs[2][3];
+  for (int d = 0; d < 3; ++d) {
+    bufs[0][d] = static_cast<TF*>(out->u_tilde[d]);
+    bufs[1][d] = P->at<TF>(P->o_mit[d]);
+  }
+  Scalars hs{};
+  double bb = 0.0, rr = 0.0;
+  bool converged = false;
+  int cur = 0, it = 0;
+  for (it = 0; it < max_iter; ++it) {
+    for (int d = 0; d < 3; ++d) {
+      ma.v[d] = bufs[cur][d];
+      ma.vf[d] = P->at<const TF>(P->o_mfv[cur][d]);
+      ma.out[d] = bufs[cur ^ 1][d];
+      ma.outf[d] = P->at<TF>(P->o_mfv[cur ^ 1][d]);
+    }
+    HIPCHK(launch(MOM_CN_ITER), "k_mom (Crank-Nicolson iteration)");
+    cur ^= 1;
+    if (int e = finalize(P, OP_RR, 0, -1, grid, 0, s)) return e;
+    log.iters++;
+    if ((it + 1) % P->o.check_every != 0 && it + 1 < max_iter) continue;
+    if (int e = read_scalars(P, &hs, s)) return e;
+    bb = hs.bb;
+    rr = hs.rr;
+    if (!std::isfinite(rr) || !std::isfinite(bb)) {
+      set_error("bcm_momentum: non-finite residual of the Crank-Nicolson iteration");
+      return BCM_ERR_NONFINITE;
+    }
+    const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    log.push(rel);
+    if (rr <= tol * tol * bb) {
+      converged = true;
+      ++it;
+      break;
+    }
+  }
+  if (cur == 1)  // the last iterate is in the plan's buffer
+    for (int d = 0; d < 3; ++d)
+      HIPCHK(hipMemcpyAsync(out->u_tilde[d], bufs[1][d], P->cells * sizeof(TF), hipMemcpyDeviceToDevice, s),
+             "copy iterate");
+  const int status = converged ? BCM_OK : BCM_NOT_CONVERGED;
+  if (rep) {
+    rep->status = status;
+    rep->n_outer = 0;
+    rep->n_inner = log.iters;
+    rep->final_rel_res = bb > 0 ? std::sqrt(std::max(rr, 0.0) / bb) : 0.0;
+  }
+  return status;
+}
+
 // Upload the cube-graph hierarchy (converted to the inner precision T) and its level table.
 template <typename T>
 int upload_graph(bcm_plan* P, hipStream_t s) {
@@ -901,6 +1017,17 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
     P->o_b[l] = take(top, nc * NL * NL * NL * Ti);
     P->o_xf[0][l] = take(top, size_t(face_stride(int(NL))) * nc * Ti);
     P->o_xf[1][l] = take(top, size_t(face_stride(int(NL))) * nc * Ti);
+  }
+  P->momentum = !M.multilevel && M.n >= 4;
+  if (P->momentum) {
+    const size_t mfs = size_t(12) * M.n * M.n * nc * Tf;
+    for (int d = 0; d < 3; ++d) {
+      P->o_mfa[d] = take(top, mfs);
+      P->o_mfv[0][d] = take(top, mfs);
+      P->o_mfv[1][d] = take(top, mfs);
+      P->o_mrhs[d] = take(top, cells * Tf);
+      P->o_mit[d] = take(top, cells * Tf);
+    }
   }
   P->graph = o.coarse_solver == 1 && M.coarse.ok && !M.coarse.levels.empty();
   if (P->graph) {
@@ -1083,6 +1210,33 @@ int bcm_project_adjoint(bcm_plan* P, const bcm_adjoint_in* in, bcm_adjoint_out* 
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   st = P->fields32 ? adjoint_impl<float>(P, in, out, rep, s) : adjoint_impl<double>(P, in, out, rep, s);
+  if (rep) rep->status = st;
+  return st;
+}
+
+int bcm_momentum(bcm_plan* P, const bcm_momentum_in* in, bcm_momentum_out* out, bcm_report* rep,
+                 void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!in || !out || !in->u[0] || !in->u[1] || !in->u[2] || !out->u_tilde[0] || !out->u_tilde[1] ||
+      !out->u_tilde[2] || !(in->dt > 0) || !(in->nu >= 0) || !std::isfinite(in->U_in) ||
+      in->scheme < BCM_EULER || in->scheme > BCM_CN || in->cn_tol < 0 || in->cn_max_iter < 0 ||
+      (in->h_prev[0] || in->h_prev[1] || in->h_prev[2]) != (in->h_prev[0] && in->h_prev[1] && in->h_prev[2]) ||
+      (out->h[0] || out->h[1] || out->h[2]) != (out->h[0] && out->h[1] && out->h[2])) {
+    set_error("bcm_momentum: NULL field, dt <= 0, nu < 0, unknown scheme or a partial field triple");
+    return BCM_ERR_INVALID_ARG;
+  }
+  if (!P->momentum) {
+    set_error("bcm_momentum: single-level meshes with n >= 4 only");
+    return BCM_ERR_UNSUPPORTED;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (out->u_tilde[d] == in->u[d]) {
+      set_error("bcm_momentum: u_tilde must not alias u");
+      return BCM_ERR_INVALID_ARG;
+    }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = P->fields32 ? momentum_impl<float>(P, in, out, rep, s) : momentum_impl<double>(P, in, out, rep, s);
   if (rep) rep->status = st;
   return st;
 }
