@@ -296,6 +296,20 @@ int bcm_momentum(bcm_plan* plan, const bcm_momentum_in* in, bcm_momentum_out* ou
 int bcm_kinetic_energy(bcm_plan* plan, const void* const u[3], double rho, double g_scale,
                        double* J, void* const g_u[3], void* stream);
 
+/* bcm_kinetic_energy for callers that cannot allocate device memory at the time of the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, the same kernels and the same results bit for bit, but the reduction's
+ * scratch (2048 partial sums and one scalar block, 16.5 KB) is a file-scope device array of the
+ * library instead of the plan's workspace; the plan must still be bound (at set-up) for the
+ * cube metadata.  The call allocates nothing: the first call on a device looks up that
+ * device's copy of the array (held until the process ends); J is read back with a copy and a
+ * stream synchronisation.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (other threads, other streams) race; nothing in the array needs clearing
+ * (each call overwrites what it reads).  Errors as bcm_kinetic_energy, plus
+ * BCM_ERR_UNSUPPORTED for a device index >= 64. */
+int bcm_kinetic_energy_noalloc(bcm_plan* plan, const void* const u[3], double rho, double g_scale,
+                               double* J, void* const g_u[3], void* stream);
+
 /* Solve the pressure Poisson equation A p = b (Sec. 3) for a device FP64 right-hand side;
  * d_p holds the initial guess on entry if use_guess != 0 (else zero) and the solution on
  * exit. */

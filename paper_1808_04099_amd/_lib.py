@@ -88,6 +88,8 @@ EXPORTS = {
                              POINTER(Report), c_void_p]),
     "bcm_kinetic_energy": (c_int, [c_void_p, POINTER(c_void_p), c_double, c_double,
                                    POINTER(c_double), POINTER(c_void_p), c_void_p]),
+    "bcm_kinetic_energy_noalloc": (c_int, [c_void_p, POINTER(c_void_p), c_double, c_double,
+                                           POINTER(c_double), POINTER(c_void_p), c_void_p]),
     "bcm_timing_enable": (c_int, [c_void_p, c_char_p]),
     "bcm_timing_read": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_double)]),
     "bcm_timing_name": (c_char_p, [c_int]),

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -854,6 +855,75 @@ int momentum_impl(bcm_plan* P, const bcm_momentum_in* in, bcm_momentum_out* out,
   return status;
 }
 
+// ---- no-allocation variant of the kinetic-energy objective --------------------------------
+// Its scratch (the per-workgroup partial sums and the scalar block of the final sum) lives in a
+// file-scope device array instead of the plan's workspace.  Every GPU that runs it holds its own
+// copy of the array until the process ends; host code reaches a device's copy only through the
+// address hipGetSymbolAddress returns with that device current (kept per device below), never
+// through the array's name.
+constexpr int kNoAllocParts = 2048;  // partial sums (the objective's grid never exceeds it)
+constexpr size_t kNoAllocBytes = kNoAllocParts * sizeof(double) + sizeof(Scalars);
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up once per device).
+int scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("bcm_kinetic_energy_noalloc: device index beyond the supported 64");
+    return BCM_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BCM_OK;
+}
+
+template <typename TF>
+int kinetic_noalloc_impl(bcm_plan* P, const void* const u[3], double rho, double g_scale, double* J,
+                         void* const g_u[3], hipStream_t s) {
+  void* base = nullptr;
+  if (int e = scratch_address(&base)) return e;
+  double* part = static_cast<double*>(base);
+  Scalars* sc = reinterpret_cast<Scalars*>(static_cast<char*>(base) + kNoAllocParts * sizeof(double));
+  KineticArgs<TF> ka{};
+  ka.meta = P->at<const CubeMeta>(P->o_meta);
+  ka.n_cubes = P->nc;
+  ka.n3 = P->n * P->n * P->n;
+  for (int d = 0; d < 3; ++d) {
+    ka.u[d] = static_cast<const TF*>(u[d]);
+    ka.gu[d] = g_u ? static_cast<TF*>(g_u[d]) : nullptr;
+  }
+  ka.gscale = g_scale * rho;
+  const int grid = std::min(P->nc, 2048);  // the same grid as bcm_kinetic_energy
+  if (grid > kNoAllocParts) {
+    set_error("bcm_kinetic_energy_noalloc: more partial sums than the scratch array holds");
+    return BCM_ERR_UNSUPPORTED;
+  }
+  ka.part = J ? part : nullptr;
+  HIPCHK(launch_kinetic<TF>(ka, grid, s), "k_kinetic");
+  if (!J) return BCM_OK;
+  FinalizeArgs fa{part, nullptr, grid, sc, OP_VUU, 0, nullptr, 0u};
+  HIPCHK(launch_finalize(fa, s), "k_finalize");
+  double vuu = 0.0;
+  HIPCHK(hipMemcpyAsync(&vuu, &sc->vuu, sizeof(double), hipMemcpyDeviceToHost, s), "objective readback");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  if (!std::isfinite(vuu)) {
+    set_error("bcm_kinetic_energy_noalloc: non-finite velocity");
+    return BCM_ERR_NONFINITE;
+  }
+  *J = 0.5 * rho * vuu;
+  return BCM_OK;
+}
+
 // Upload the cube-graph hierarchy (converted to the inner precision T) and its level table.
 template <typename T>
 int upload_graph(bcm_plan* P, hipStream_t s) {
@@ -1253,6 +1323,20 @@ int bcm_kinetic_energy(bcm_plan* P, const void* const u[3], double rho, double g
   hipStream_t s = static_cast<hipStream_t>(stream);
   return P->fields32 ? kinetic_impl<float>(P, u, rho, g_scale, J, g_u, s)
                      : kinetic_impl<double>(P, u, rho, g_scale, J, g_u, s);
+}
+
+int bcm_kinetic_energy_noalloc(bcm_plan* P, const void* const u[3], double rho, double g_scale,
+                               double* J, void* const g_u[3], void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!u || !u[0] || !u[1] || !u[2] || !(rho > 0) || !std::isfinite(g_scale) ||
+      (g_u && (!g_u[0] || !g_u[1] || !g_u[2]))) {
+    set_error("bcm_kinetic_energy_noalloc: NULL field, non-positive rho or non-finite g_scale");
+    return BCM_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return P->fields32 ? kinetic_noalloc_impl<float>(P, u, rho, g_scale, J, g_u, s)
+                     : kinetic_noalloc_impl<double>(P, u, rho, g_scale, J, g_u, s);
 }
 
 int bcm_poisson_solve(bcm_plan* P, const double* d_b, double* d_p, int use_guess, bcm_report* rep,
