@@ -14,6 +14,8 @@ never does, and shares no code with it.
                  assemble)
   momentum.py    the momentum sub-step (QUICK convection, diffusion; Euler, AB2, Crank-Nicolson)
                  on single-level meshes, array form with two-layer ghost cells
+  lagrangian.py  the Lagrangian-particle forcing: 3-point discrete delta interpolation, constraint
+                 force and spreading, as an assembled particle x cell weight matrix
   composite.py   the Laplacian, divergence and residual norm of any mesh as whole-array
                  expressions over the cube-major fields (full-size residuals of the 3-level mesh)
 
