@@ -200,3 +200,22 @@ def _fourier_field_uniform(mesh: Mesh, k, a, phi, L):
         x, y, z = cijk[c]
         out[c] = G[z * n:(z + 1) * n, y * n:(y + 1) * n, x * n:(x + 1) * n]
     return out
+
+
+# ---------------------------------------------------------------------------------------------
+# Surface particles of an immersed body (the paper's Lagrangian points: about one per Eulerian
+# cell that the surface crosses).
+# ---------------------------------------------------------------------------------------------
+def sphere_particles(centre, radius, spacing):
+    """Points on a sphere on a Fibonacci lattice with about one point per spacing^2 of surface,
+    and the Lagrangian volume of each (its surface share times the spacing): (X [n, 3], dV [n])."""
+    area = 4.0 * np.pi * radius ** 2
+    n = max(1, int(round(area / spacing ** 2)))
+    k = np.arange(n, dtype=np.float64) + 0.5
+    z = 1.0 - 2.0 * k / n
+    r = np.sqrt(np.maximum(1.0 - z * z, 0.0))
+    ang = np.pi * (3.0 - np.sqrt(5.0)) * k
+    X = np.asarray(centre, dtype=np.float64)[None, :] + radius * np.stack(
+        [r * np.cos(ang), r * np.sin(ang), z], axis=1)
+    dV = np.full(n, area / n * spacing)
+    return X, dV

@@ -231,6 +231,17 @@ typedef struct {
   void* h[3];             /* optional: H(u^n) (the next AB2 step's h_prev), or all NULL */
 } bcm_momentum_out;
 
+/* Surface particles of an immersed body (Sec. 2.3): positions, Lagrangian volumes and the body
+ * velocity at each particle. */
+typedef struct {
+  int32_t n;              /* number of particles (>= 0) */
+  const double* X;        /* [n][3] positions (device, FP64) */
+  const double* dV;       /* [n] Lagrangian volume dc_1 dc_2 dc_3 of each particle (device), or
+                             NULL for h^3 of the cell that holds it */
+  const double* Us;       /* [n][3] body velocity at the particles (device), or NULL: us_const */
+  double us_const[3];
+} bcm_particles;
+
 /* Fill opts with the defaults listed in bcm_solver_opts. */
 void bcm_default_opts(bcm_solver_opts* opts);
 
@@ -280,6 +291,26 @@ int bcm_project_adjoint(bcm_plan* plan, const bcm_adjoint_in* in, bcm_adjoint_ou
  * BCM_ERR_NONFINITE if a norm is not finite.  report may be NULL. */
 int bcm_momentum(bcm_plan* plan, const bcm_momentum_in* in, bcm_momentum_out* out,
                  bcm_report* report, void* stream);
+
+/* Forcing sub-step with Lagrangian particles (Sec. 3; Eqs. (ddeltai), (ddeltap)): every particle
+ * interpolates u~ with the 3-point smoothed discrete delta function of Sec. 2.4 over the
+ * 3 x 3 x 3 cells around the cell that holds it, U_p = sum_i u~_i prod_n phi((x_i,n - X_p,n)/h),
+ * takes the constraint force F_p = (rho/dt)(U_s,p - U_p), and spreads it back with the same
+ * weights: u* = u~ + (dt/rho) f, f_i = sum_p F_p prod_n phi(...) dV_p / h^3.  A particle's cell
+ * is found on the finest level that has a cube there; its support must lie in cubes of that
+ * level inside the domain.  The spread is added with atomics, so cells shared by several
+ * particles are summed in no fixed order (results reproducible to rounding only).
+ *   u_tilde / u_star  three device fields of the field type each (u_star written; must not
+ *                     alias u_tilde)
+ *   U_p, F_p          optional [n][3] device FP64 outputs (interpolated velocity, force), or NULL
+ * Errors: BCM_ERR_INVALID_ARG (NULL or aliased fields, dt or rho not positive; or particles
+ * outside the mesh or with a support leaving their level or the domain: those are skipped, the
+ * others' forcing is in u_star, and bcm_last_error gives the count), BCM_ERR_UNSUPPORTED (no
+ * point-location tables: a level's cubes span more than 2^26 lattice positions).  The call
+ * waits for the stream (it reads the skip count back). */
+int bcm_ib_force(bcm_plan* plan, const bcm_particles* particles, const void* const u_tilde[3],
+                 void* const u_star[3], double dt, double rho, double* U_p, double* F_p,
+                 void* stream);
 
 /* Objective of the differentiable multi-step projection: the kinetic energy of a cell-centred
  * velocity field, J = (rho/2) sum_i V_i |u_i|^2 with V_i = h_i^3 the cell volume (the paper

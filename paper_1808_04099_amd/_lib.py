@@ -67,6 +67,11 @@ class MomentumOut(ctypes.Structure):
 
 SCHEMES = {"euler": 0, "ab2": 1, "cn": 2}
 
+
+class Particles(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("X", c_void_p), ("dV", c_void_p), ("Us", c_void_p),
+                ("us_const", c_double * 3)]
+
 EXPORTS = {
     "bcm_default_opts": (None, [POINTER(SolverOpts)]),
     "bcm_mesh_create": (c_int, [POINTER(MeshDesc), POINTER(c_void_p)]),
@@ -84,6 +89,8 @@ EXPORTS = {
     "bcm_poisson_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_int, POINTER(Report),
                                   c_void_p]),
     "bcm_apply_laplacian": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "bcm_ib_force": (c_int, [c_void_p, POINTER(Particles), POINTER(c_void_p), POINTER(c_void_p),
+                             c_double, c_double, c_void_p, c_void_p, c_void_p]),
     "bcm_momentum": (c_int, [c_void_p, POINTER(MomentumIn), POINTER(MomentumOut),
                              POINTER(Report), c_void_p]),
     "bcm_kinetic_energy": (c_int, [c_void_p, POINTER(c_void_p), c_double, c_double,

@@ -263,6 +263,30 @@ class Plan:
         _check(st, "bcm_momentum")
         return dict(u_tilde=ut, h=h, report=_unpack(rep, hist))
 
+    def ib_force(self, u, X, dt, rho, dV=None, Us=(0.0, 0.0, 0.0), want_UF=False, out=None):
+        """Lagrangian-particle forcing u~ -> u*; X, dV, Us: contiguous device float64 tensors
+        (3n, n and 3n values, particle-major) or Us a constant triple.  Returns dict(u_star=[3], U_p, F_p ([n, 3] or None))."""
+        u = [self._field(x, f"u[{d}]") for d, x in enumerate(u)]
+        n = int(X.numel()) // 3 if X is not None else 0
+        if X is not None and X.numel() != 3 * n:
+            raise ValueError("X: expected 3 coordinates per particle")
+        for t, name in ((X, "X"), (dV, "dV")) + (((Us, "Us"),) if torch.is_tensor(Us) else ()):
+            if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor")
+        usc = (0.0, 0.0, 0.0) if torch.is_tensor(Us) else tuple(float(v) for v in Us)
+        pt = L.Particles(n, _ptr(X).value, _ptr(dV).value,
+                         _ptr(Us).value if torch.is_tensor(Us) else None,
+                         (ctypes.c_double * 3)(*usc))
+        us = out or [self.empty() for _ in range(3)]
+        Up = torch.empty((n, 3), dtype=torch.float64, device=self.device) if want_UF else None
+        Fp = torch.empty((n, 3), dtype=torch.float64, device=self.device) if want_UF else None
+        st = self._lib.bcm_ib_force(self.handle, ctypes.byref(pt),
+                                    (ctypes.c_void_p * 3)(*[x.data_ptr() for x in u]),
+                                    (ctypes.c_void_p * 3)(*[x.data_ptr() for x in us]),
+                                    float(dt), float(rho), _ptr(Up), _ptr(Fp), _stream())
+        _check(st, "bcm_ib_force", allow_warning=False)
+        return dict(u_star=us, U_p=Up, F_p=Fp)
+
     def kinetic_energy(self, u, rho, g_scale=None, want_J=True):
         """J = (rho/2) sum_i V_i |u_i|^2 (host float, or None with want_J=False) and, when
         g_scale is given, the seed cotangent g_scale * rho * V * u (three fields; else None)."""

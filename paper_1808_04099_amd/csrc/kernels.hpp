@@ -245,6 +245,38 @@ struct MomArgs {
   double* part;
 };
 
+// Lagrangian-particle forcing (kernels_ib.hip).  Point location: per refinement level present
+// (finest first), a dense table over the bounding box of that level's cubes on its lattice,
+// anchored at the minimum corner of the coarsest level's cubes; entry = cube index or -1.
+struct IbLevel {
+  int level;
+  int lo[3], dims[3];     // lattice position of the table's first entry and its extent
+  long long offset;       // first entry in the table array
+  double edge;            // cube edge of the level
+};
+constexpr int kIbMaxLevels = 24;
+
+template <typename TF>
+struct IbArgs {
+  const CubeMeta* meta;
+  int n_cubes, n;
+  const int32_t* table;
+  IbLevel lev[kIbMaxLevels];
+  int n_levels;
+  double anchor[3];
+  int n_particles;
+  const double* X;        // [n_particles][3]
+  const double* dV;       // [n_particles] or nullptr (h^3)
+  const double* Us;       // [n_particles][3] or nullptr (usc)
+  double usc[3];
+  const TF* u[3];         // u~ (read)
+  TF* ustar[3];           // u* (holds u~ on entry; the spread is added)
+  double rho_dt, dt_rho;
+  double* Up;             // [n_particles][3] or nullptr
+  double* Fp;             // [n_particles][3] or nullptr
+  unsigned int* errors;   // particles skipped (outside the mesh, or support leaving one level)
+};
+
 struct ScaleArgs {      // y = x * (vol ^ power) per cube (power = +1 or -1)
   const CubeMeta* meta;
   int n_cubes, n3;
@@ -270,6 +302,8 @@ template <typename TF> hipError_t launch_adj_rhs(int NL, const AdjRhsArgs<TF>& a
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 template <typename TF> hipError_t launch_kinetic(const KineticArgs<TF>& a, int grid, hipStream_t s);
 template <typename TF> hipError_t launch_mom_export(int NL, const MomExportArgs<TF>& a, int grid, hipStream_t s);
+template <typename TF> hipError_t launch_ib_force(const IbArgs<TF>& a, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int* p, hipStream_t s);
 template <typename TF> hipError_t launch_mom(int NL, int mode, const MomArgs<TF>& a, int grid, hipStream_t s);
 template <typename T> hipError_t launch_coarse_mg(const CoarseMGArgs<T>& a, hipStream_t s);
 // Multi-workgroup steps on one large graph level; n = lanes (cubes, nodes of the range, nodes

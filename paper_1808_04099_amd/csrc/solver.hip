@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -45,7 +46,7 @@ const char* const kTimerNames[] = {"presmooth16", "presmooth8", "presmooth4", "p
                                    "restrict8", "restrict4", "restrict2", "apply16", "apply8",
                                    "apply4", "apply2", "update", "resid64", "ir", "coarse",
                                    "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
-                                   "export", "xupdate", "momentum", nullptr};
+                                   "export", "xupdate", "momentum", "ib", nullptr};
 
 int level_index(int NL) { return NL == 16 ? 0 : NL == 8 ? 1 : NL == 4 ? 2 : 3; }
 
@@ -82,6 +83,12 @@ struct bcm_plan {
   size_t o_mfa[3] = {0, 0, 0}, o_mfv[2][3] = {{0, 0, 0}, {0, 0, 0}}, o_mrhs[3] = {0, 0, 0},
          o_mit[3] = {0, 0, 0};
   bool momentum = false;
+  // Lagrangian-particle forcing: per-level point-location tables (finest level first)
+  std::vector<int32_t> ib_table;
+  std::vector<IbLevel> ib_levels;
+  double ib_anchor[3] = {0, 0, 0};
+  size_t o_ibtab = 0, o_iberr = 0;
+  bool ib = false;
   size_t o_ustar[3] = {0, 0, 0}, o_uf = 0, o_b64 = 0, o_pf = 0, o_lam = 0;
   size_t o_r = 0, o_z = 0, o_p = 0, o_q = 0, o_d = 0;
   size_t o_zf[2] = {0, 0}, o_pfk[2] = {0, 0};
@@ -855,6 +862,47 @@ int momentum_impl(bcm_plan* P, const bcm_momentum_in* in, bcm_momentum_out* out,
   return status;
 }
 
+// Lagrangian-particle forcing: u* = u~, then every particle adds its spread constraint force.
+template <typename TF>
+int ib_force_impl(bcm_plan* P, const bcm_particles* pt, const void* const u_tilde[3], void* const u_star[3],
+                  double dt, double rho, double* Up, double* Fp, hipStream_t s) {
+  IbArgs<TF> a{};
+  a.meta = P->at<const CubeMeta>(P->o_meta);
+  a.n_cubes = P->nc;
+  a.n = P->n;
+  a.table = P->at<const int32_t>(P->o_ibtab);
+  a.n_levels = int(P->ib_levels.size());
+  for (int l = 0; l < a.n_levels; ++l) a.lev[l] = P->ib_levels[l];
+  for (int d = 0; d < 3; ++d) {
+    a.anchor[d] = P->ib_anchor[d];
+    a.usc[d] = pt->us_const[d];
+    a.u[d] = static_cast<const TF*>(u_tilde[d]);
+    a.ustar[d] = static_cast<TF*>(u_star[d]);
+    HIPCHK(hipMemcpyAsync(u_star[d], u_tilde[d], P->cells * sizeof(TF), hipMemcpyDeviceToDevice, s), "copy u~");
+  }
+  a.n_particles = pt->n;
+  a.X = pt->X;
+  a.dV = pt->dV;
+  a.Us = pt->Us;
+  a.rho_dt = rho / dt;
+  a.dt_rho = dt / rho;
+  a.Up = Up;
+  a.Fp = Fp;
+  a.errors = P->at<unsigned int>(P->o_iberr);
+  HIPCHK(launch_zero_u32(a.errors, s), "zero the skip counter");
+  HIPCHK(timed(P, cls_of("ib", 0), s, [&] { return launch_ib_force<TF>(a, s); }), "k_ib_force");
+  unsigned int skipped = 0;
+  HIPCHK(hipMemcpyAsync(&skipped, a.errors, sizeof(skipped), hipMemcpyDeviceToHost, s), "skip counter readback");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  if (skipped) {
+    set_error("bcm_ib_force: " + std::to_string(skipped) +
+              " particles skipped (outside the mesh, or their 3x3x3 support leaves their cube's level"
+              " or the domain); u_star holds the forcing of the others");
+    return BCM_ERR_INVALID_ARG;
+  }
+  return BCM_OK;
+}
+
 // ---- no-allocation variant of the kinetic-energy objective --------------------------------
 // Its scratch (the per-workgroup partial sums and the scalar block of the final sum) lives in a
 // file-scope device array instead of the plan's workspace.  Every GPU that runs it holds its own
@@ -1099,6 +1147,64 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
       P->o_mit[d] = take(top, cells * Tf);
     }
   }
+  // point-location tables of the particle forcing: per level, a dense table over the bounding
+  // box of its cubes on its lattice (skipped when a level's box exceeds 2^26 entries)
+  {
+    int lmin = 127, lmax = -1;
+    for (int c = 0; c < int(nc); ++c) {
+      lmin = std::min<int>(lmin, M.level[c]);
+      lmax = std::max<int>(lmax, M.level[c]);
+    }
+    for (int d = 0; d < 3; ++d) P->ib_anchor[d] = HUGE_VAL;
+    for (int c = 0; c < int(nc); ++c)
+      if (M.level[c] == lmin)
+        for (int d = 0; d < 3; ++d) P->ib_anchor[d] = std::min(P->ib_anchor[d], M.origin[3 * c + d]);
+    bool ok = lmax >= 0 && lmax - lmin + 1 <= kIbMaxLevels;
+    for (int L = lmax; L >= lmin && ok; --L) {
+      IbLevel lv{};
+      lv.level = L;
+      lv.edge = M.root_edge / std::ldexp(1.0, L);
+      int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+      bool any = false;
+      for (int c = 0; c < int(nc); ++c) {
+        if (M.level[c] != L) continue;
+        any = true;
+        for (int d = 0; d < 3; ++d) {
+          const int q = int(std::lround((M.origin[3 * c + d] - P->ib_anchor[d]) / lv.edge));
+          lo[d] = std::min(lo[d], q);
+          hi[d] = std::max(hi[d], q);
+        }
+      }
+      if (!any) continue;
+      long long cnt = 1;
+      for (int d = 0; d < 3; ++d) {
+        lv.lo[d] = lo[d];
+        lv.dims[d] = hi[d] - lo[d] + 1;
+        cnt *= lv.dims[d];
+      }
+      if (cnt > (1LL << 26)) {
+        ok = false;
+        break;
+      }
+      lv.offset = (long long)P->ib_table.size();
+      P->ib_table.resize(P->ib_table.size() + size_t(cnt), -1);
+      for (int c = 0; c < int(nc); ++c) {
+        if (M.level[c] != L) continue;
+        int q[3];
+        for (int d = 0; d < 3; ++d) q[d] = int(std::lround((M.origin[3 * c + d] - P->ib_anchor[d]) / lv.edge)) - lv.lo[d];
+        P->ib_table[size_t(lv.offset + ((long long)q[2] * lv.dims[1] + q[1]) * lv.dims[0] + q[0])] = c;
+      }
+      P->ib_levels.push_back(lv);
+    }
+    P->ib = ok && !P->ib_levels.empty();
+    if (P->ib) {
+      P->o_ibtab = take(top, P->ib_table.size() * sizeof(int32_t));
+      P->o_iberr = take(top, 256);
+    } else {
+      P->ib_table.clear();
+      P->ib_levels.clear();
+    }
+  }
   P->graph = o.coarse_solver == 1 && M.coarse.ok && !M.coarse.levels.empty();
   if (P->graph) {
     const auto& Ls = M.coarse.levels;
@@ -1196,6 +1302,9 @@ int bcm_plan_bind(bcm_plan* P, void* d_ws, size_t bytes, void* stream) {
   if (P->o_nb27)
     HIPCHK(hipMemcpyAsync(P->ws + P->o_nb27, M.nb27.data(), M.nb27.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice, s), "upload 27-neighbourhoods");
+  if (P->ib)
+    HIPCHK(hipMemcpyAsync(P->ws + P->o_ibtab, P->ib_table.data(), P->ib_table.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s), "upload point-location tables");
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   if (!P->mirror) {
     // pinned, coherent host memory for the scalar mirror; without it the scalars are copied
@@ -1323,6 +1432,28 @@ int bcm_kinetic_energy(bcm_plan* P, const void* const u[3], double rho, double g
   hipStream_t s = static_cast<hipStream_t>(stream);
   return P->fields32 ? kinetic_impl<float>(P, u, rho, g_scale, J, g_u, s)
                      : kinetic_impl<double>(P, u, rho, g_scale, J, g_u, s);
+}
+
+int bcm_ib_force(bcm_plan* P, const bcm_particles* pt, const void* const u_tilde[3], void* const u_star[3],
+                 double dt, double rho, double* U_p, double* F_p, void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!pt || !u_tilde || !u_star || pt->n < 0 || (pt->n > 0 && !pt->X) || !(dt > 0) || !(rho > 0)) {
+    set_error("bcm_ib_force: NULL argument, negative particle count, or dt / rho not positive");
+    return BCM_ERR_INVALID_ARG;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (!u_tilde[d] || !u_star[d] || u_tilde[d] == u_star[d]) {
+      set_error("bcm_ib_force: NULL field, or u_star aliasing u_tilde");
+      return BCM_ERR_INVALID_ARG;
+    }
+  if (!P->ib) {
+    set_error("bcm_ib_force: no point-location tables for this mesh (a level's bounding box is too large)");
+    return BCM_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return P->fields32 ? ib_force_impl<float>(P, pt, u_tilde, u_star, dt, rho, U_p, F_p, s)
+                     : ib_force_impl<double>(P, pt, u_tilde, u_star, dt, rho, U_p, F_p, s);
 }
 
 int bcm_kinetic_energy_noalloc(bcm_plan* P, const void* const u[3], double rho, double g_scale,
