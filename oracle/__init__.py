@@ -16,6 +16,8 @@ never does, and shares no code with it.
                  on single-level meshes, array form with two-layer ghost cells
   lagrangian.py  the Lagrangian-particle forcing: 3-point discrete delta interpolation, constraint
                  force and spreading, as an assembled particle x cell weight matrix
+  codec.py       per-cube lossy wavelet compression of checkpoints (CDF 5/3 lifting, uniform
+                 quantisation, adaptive bit packing) and its byte stream
   composite.py   the Laplacian, divergence and residual norm of any mesh as whole-array
                  expressions over the cube-major fields (full-size residuals of the 3-level mesh)
 
