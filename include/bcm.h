@@ -312,6 +312,33 @@ int bcm_ib_force(bcm_plan* plan, const bcm_particles* particles, const void* con
                  void* const u_star[3], double dt, double rho, double* U_p, double* F_p,
                  void* stream);
 
+/* Lossy compression of an FP64 cell field for checkpoints (Sec. 6.4.1, Alg. "Compression
+ * algorithm"): each cube transformed on its own by the CDF 5/3 wavelet (lifting along x, y, z,
+ * log2(n) levels, symmetric extension at the cube faces), the coefficients quantised with one
+ * uniform step (round half to even), the codes stored in groups of 32 at the group's bit width
+ * (zigzag map), the cubes' streams concatenated behind a header of per-cube offsets:
+ *   0 "BCMW" | 4 version 1 | 8 number of cubes | 12 n | 16 levels | 20 zero | 24 step (FP64) |
+ *   32 (number of cubes + 1) u64 offsets relative to the data start | data: per cube the
+ *   n^3/32 group widths (bytes, zero-padded to 4), then each group's w 32-bit words, code j at
+ *   bits j w .. j w + w - 1 (little-endian).
+ * Each cell of the decoded field differs from the original by at most gain * step / 2, gain =
+ * the row-sum norm of the inverse transform (24.375 for n = 16).  Meshes with n >= 4 only
+ * (else BCM_ERR_UNSUPPORTED).  The calls use the plan's Krylov vectors as scratch and wait for
+ * the stream at their readbacks. */
+/* Worst-case stream size of the plan's mesh (host only). */
+int bcm_compress_bound(const bcm_plan* plan, size_t* bytes);
+/* Compress the device field d_field (n_cubes * n^3 FP64) into d_stream (device, 8-byte aligned,
+ * capacity bytes); *bytes = the stream's size.  BCM_ERR_INVALID_ARG if the buffer is too small
+ * (the needed size is in *bytes; nothing past the header written), if step is not positive and
+ * finite, or if a code would reach 2^30 (step too small for the field) or a value is not finite. */
+int bcm_compress(bcm_plan* plan, const double* d_field, double step, void* d_stream,
+                 size_t capacity, size_t* bytes, void* stream);
+/* Decompress a stream of this mesh (device, 8-byte aligned, bytes long) into d_field.
+ * BCM_ERR_INVALID_ARG if the header does not match the mesh or a cube's stream is malformed
+ * (those cubes decode to zero). */
+int bcm_decompress(bcm_plan* plan, const void* d_stream, size_t bytes, double* d_field,
+                   void* stream);
+
 /* Objective of the differentiable multi-step projection: the kinetic energy of a cell-centred
  * velocity field, J = (rho/2) sum_i V_i |u_i|^2 with V_i = h_i^3 the cell volume (the paper
  * states no normalisation for it; this is the discrete form on the mesh's cells), summed in

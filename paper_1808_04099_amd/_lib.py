@@ -89,6 +89,10 @@ EXPORTS = {
     "bcm_poisson_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_int, POINTER(Report),
                                   c_void_p]),
     "bcm_apply_laplacian": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "bcm_compress_bound": (c_int, [c_void_p, POINTER(c_size_t)]),
+    "bcm_compress": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_size_t, POINTER(c_size_t),
+                             c_void_p]),
+    "bcm_decompress": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "bcm_ib_force": (c_int, [c_void_p, POINTER(Particles), POINTER(c_void_p), POINTER(c_void_p),
                              c_double, c_double, c_void_p, c_void_p, c_void_p]),
     "bcm_momentum": (c_int, [c_void_p, POINTER(MomentumIn), POINTER(MomentumOut),

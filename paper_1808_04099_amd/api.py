@@ -287,6 +287,28 @@ class Plan:
         _check(st, "bcm_ib_force", allow_warning=False)
         return dict(u_star=us, U_p=Up, F_p=Fp)
 
+    def compress(self, field, step, out=None):
+        """Wavelet-compress an FP64 cell field; returns the stream as a device uint8 tensor (a
+        view of `out` when given, else of a buffer of the worst-case size)."""
+        field = self._field(field, "field", torch.float64)
+        bound = ctypes.c_size_t()
+        _check(self._lib.bcm_compress_bound(self.handle, ctypes.byref(bound)),
+               "bcm_compress_bound", allow_warning=False)
+        buf = out if out is not None else torch.empty(bound.value, dtype=torch.uint8,
+                                                      device=self.device)
+        n = ctypes.c_size_t()
+        _check(self._lib.bcm_compress(self.handle, _ptr(field), float(step), _ptr(buf),
+                                      buf.numel(), ctypes.byref(n), _stream()),
+               "bcm_compress", allow_warning=False)
+        return buf[:n.value]
+
+    def decompress(self, stream, out=None):
+        """Decode a stream (device uint8 tensor) into an FP64 cell field."""
+        out = self.empty(torch.float64) if out is None else self._field(out, "out", torch.float64)
+        _check(self._lib.bcm_decompress(self.handle, _ptr(stream), stream.numel(), _ptr(out),
+                                        _stream()), "bcm_decompress", allow_warning=False)
+        return out
+
     def kinetic_energy(self, u, rho, g_scale=None, want_J=True):
         """J = (rho/2) sum_i V_i |u_i|^2 (host float, or None with want_J=False) and, when
         g_scale is given, the seed cotangent g_scale * rho * V * u (three fields; else None)."""

@@ -20,7 +20,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 OBJ_DIR = os.path.join(OUT_DIR, "obj")
 LIB = os.path.join(OUT_DIR, "libbcm.so")
 SOURCES = ["mesh.cpp", "coarse.cpp", "kernels_mg.hip", "kernels_col.hip", "kernels_proj.hip",
-           "kernels_mom.hip", "kernels_ib.hip", "solver.hip"]
+           "kernels_mom.hip", "kernels_ib.hip", "kernels_codec.hip", "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -277,6 +277,26 @@ struct IbArgs {
   unsigned int* errors;   // particles skipped (outside the mesh, or support leaving one level)
 };
 
+// Wavelet compression of an FP64 cell field (kernels_codec.hip).
+struct CodecArgs {
+  int n_cubes, n, levels;
+  double step;
+  const double* field;          // encode input
+  uint32_t* codes;              // [n_cubes][n^3] zigzag codes (workspace)
+  uint8_t* widths;              // [n_cubes][n^3 / 32] group bit widths (workspace)
+  unsigned long long* sizes;    // [n_cubes] stream bytes of each cube (workspace)
+  unsigned long long* total;    // data bytes of the whole stream (workspace)
+  void* stream;                 // encode output
+  const void* stream_in;        // decode input
+  unsigned long long data_bytes;  // decode: bytes after the header and offsets
+  double* field_out;            // decode output
+  unsigned int* flags;          // bit 0: a code beyond 2^30; bit 1: a malformed cube stream
+};
+hipError_t launch_wc_encode(int NL, const CodecArgs& a, int grid, hipStream_t s);
+hipError_t launch_wc_header(const CodecArgs& a, hipStream_t s);
+hipError_t launch_wc_pack(int NL, const CodecArgs& a, int grid, hipStream_t s);
+hipError_t launch_wc_decode(int NL, const CodecArgs& a, int grid, hipStream_t s);
+
 struct ScaleArgs {      // y = x * (vol ^ power) per cube (power = +1 or -1)
   const CubeMeta* meta;
   int n_cubes, n3;

@@ -46,7 +46,7 @@ const char* const kTimerNames[] = {"presmooth16", "presmooth8", "presmooth4", "p
                                    "restrict8", "restrict4", "restrict2", "apply16", "apply8",
                                    "apply4", "apply2", "update", "resid64", "ir", "coarse",
                                    "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
-                                   "export", "xupdate", "momentum", "ib", nullptr};
+                                   "export", "xupdate", "momentum", "ib", "codec", nullptr};
 
 int level_index(int NL) { return NL == 16 ? 0 : NL == 8 ? 1 : NL == 4 ? 2 : 3; }
 
@@ -89,6 +89,7 @@ struct bcm_plan {
   double ib_anchor[3] = {0, 0, 0};
   size_t o_ibtab = 0, o_iberr = 0;
   bool ib = false;
+  size_t o_cflag = 0;  // wavelet codec: total bytes (u64) and error flags (u32)
   size_t o_ustar[3] = {0, 0, 0}, o_uf = 0, o_b64 = 0, o_pf = 0, o_lam = 0;
   size_t o_r = 0, o_z = 0, o_p = 0, o_q = 0, o_d = 0;
   size_t o_zf[2] = {0, 0}, o_pfk[2] = {0, 0};
@@ -903,6 +904,28 @@ int ib_force_impl(bcm_plan* P, const bcm_particles* pt, const void* const u_tild
   return BCM_OK;
 }
 
+// Wavelet codec: header bytes, the worst case of a cube's stream, transform levels.
+size_t codec_header_bytes(const bcm_plan* P) { return 32 + 8 * (size_t(P->nc) + 1); }
+size_t codec_cube_bound(int n) {
+  const size_t G = size_t(n) * n * n / 32;
+  return (G + 3) / 4 * 4 + 4 * 32 * G;
+}
+int codec_levels(int n) { return n == 16 ? 4 : n == 8 ? 3 : 2; }
+
+CodecArgs codec_args(bcm_plan* P, double step) {
+  CodecArgs a{};
+  a.n_cubes = P->nc;
+  a.n = P->n;
+  a.levels = codec_levels(P->n);
+  a.step = step;
+  a.codes = P->at<uint32_t>(P->o_r);   // the Krylov vectors are free between solves
+  a.widths = P->at<uint8_t>(P->o_z);
+  a.sizes = P->at<unsigned long long>(P->o_part[1]);
+  a.total = P->at<unsigned long long>(P->o_cflag);
+  a.flags = reinterpret_cast<unsigned int*>(P->at<char>(P->o_cflag) + 8);
+  return a;
+}
+
 // ---- no-allocation variant of the kinetic-energy objective --------------------------------
 // Its scratch (the per-workgroup partial sums and the scalar block of the final sum) lives in a
 // file-scope device array instead of the plan's workspace.  Every GPU that runs it holds its own
@@ -1205,6 +1228,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
       P->ib_levels.clear();
     }
   }
+  P->o_cflag = take(top, 256);
   P->graph = o.coarse_solver == 1 && M.coarse.ok && !M.coarse.levels.empty();
   if (P->graph) {
     const auto& Ls = M.coarse.levels;
@@ -1454,6 +1478,115 @@ int bcm_ib_force(bcm_plan* P, const bcm_particles* pt, const void* const u_tilde
   hipStream_t s = static_cast<hipStream_t>(stream);
   return P->fields32 ? ib_force_impl<float>(P, pt, u_tilde, u_star, dt, rho, U_p, F_p, s)
                      : ib_force_impl<double>(P, pt, u_tilde, u_star, dt, rho, U_p, F_p, s);
+}
+
+int bcm_compress_bound(const bcm_plan* P, size_t* bytes) {
+  if (!P || !bytes) {
+    set_error("bcm_compress_bound: NULL argument");
+    return BCM_ERR_INVALID_ARG;
+  }
+  if (P->n < 4) {
+    set_error("bcm_compress_bound: the codec needs n >= 4");
+    return BCM_ERR_UNSUPPORTED;
+  }
+  *bytes = codec_header_bytes(P) + size_t(P->nc) * codec_cube_bound(P->n);
+  return BCM_OK;
+}
+
+int bcm_compress(bcm_plan* P, const double* d_field, double step, void* d_stream, size_t capacity,
+                 size_t* bytes, void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!d_field || !d_stream || !bytes || !(step > 0) || !std::isfinite(step) ||
+      (reinterpret_cast<uintptr_t>(d_stream) % 8) != 0) {
+    set_error("bcm_compress: NULL argument, step not positive and finite, or stream not 8-byte aligned");
+    return BCM_ERR_INVALID_ARG;
+  }
+  if (P->n < 4) {
+    set_error("bcm_compress: the codec needs n >= 4");
+    return BCM_ERR_UNSUPPORTED;
+  }
+  const size_t head = codec_header_bytes(P);
+  if (capacity < head) {
+    *bytes = head;
+    set_error("bcm_compress: stream buffer smaller than the header");
+    return BCM_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CodecArgs a = codec_args(P, step);
+  a.field = d_field;
+  a.stream = d_stream;
+  const int grid = std::min(P->nc, 4096);
+  HIPCHK(launch_zero_u32(a.flags, s), "zero the codec flags");
+  HIPCHK(timed(P, cls_of("codec", 0), s, [&] { return launch_wc_encode(P->n, a, grid, s); }), "k_wc_encode");
+  HIPCHK(launch_wc_header(a, s), "k_wc_header");
+  struct {
+    unsigned long long total;
+    unsigned int flags, pad;
+  } back{};
+  HIPCHK(hipMemcpyAsync(&back, a.total, sizeof(back), hipMemcpyDeviceToHost, s), "codec readback");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  if (back.flags & 1u) {
+    set_error("bcm_compress: step too small for the field (a code reaches 2^30) or a non-finite value");
+    return BCM_ERR_INVALID_ARG;
+  }
+  *bytes = head + size_t(back.total);
+  if (*bytes > capacity) {
+    set_error("bcm_compress: stream buffer too small (the needed size is in *bytes)");
+    return BCM_ERR_INVALID_ARG;
+  }
+  HIPCHK(timed(P, cls_of("codec", 0), s, [&] { return launch_wc_pack(P->n, a, grid, s); }), "k_wc_pack");
+  return BCM_OK;
+}
+
+int bcm_decompress(bcm_plan* P, const void* d_stream, size_t bytes, double* d_field, void* stream) {
+  int st = check_bound(P);
+  if (st) return st;
+  if (!d_stream || !d_field || (reinterpret_cast<uintptr_t>(d_stream) % 8) != 0) {
+    set_error("bcm_decompress: NULL argument or stream not 8-byte aligned");
+    return BCM_ERR_INVALID_ARG;
+  }
+  if (P->n < 4) {
+    set_error("bcm_decompress: the codec needs n >= 4");
+    return BCM_ERR_UNSUPPORTED;
+  }
+  const size_t head = codec_header_bytes(P);
+  if (bytes < head) {
+    set_error("bcm_decompress: stream shorter than its header");
+    return BCM_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char h[32];
+  unsigned long long last = 0;
+  HIPCHK(hipMemcpyAsync(h, d_stream, 32, hipMemcpyDeviceToHost, s), "header readback");
+  HIPCHK(hipMemcpyAsync(&last, static_cast<const char*>(d_stream) + 32 + 8 * size_t(P->nc), 8,
+                        hipMemcpyDeviceToHost, s), "header readback");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  uint32_t hw[6];
+  double step = 0;
+  std::memcpy(hw, h, 24);
+  std::memcpy(&step, h + 24, 8);
+  if (hw[0] != 0x574D4342u || hw[1] != 1u || int(hw[2]) != P->nc || int(hw[3]) != P->n ||
+      int(hw[4]) != codec_levels(P->n) || !(step > 0) || !std::isfinite(step) || last != bytes - head) {
+    set_error("bcm_decompress: not a stream of this mesh (magic, version, cube count, n, levels, "
+              "step or total size)");
+    return BCM_ERR_INVALID_ARG;
+  }
+  CodecArgs a = codec_args(P, step);
+  a.stream_in = d_stream;
+  a.data_bytes = bytes - head;
+  a.field_out = d_field;
+  HIPCHK(launch_zero_u32(a.flags, s), "zero the codec flags");
+  HIPCHK(timed(P, cls_of("codec", 0), s,
+               [&] { return launch_wc_decode(P->n, a, std::min(P->nc, 4096), s); }), "k_wc_decode");
+  unsigned int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, a.flags, sizeof(flags), hipMemcpyDeviceToHost, s), "codec readback");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  if (flags & 2u) {
+    set_error("bcm_decompress: malformed cube stream(s); those cubes decode to zero");
+    return BCM_ERR_INVALID_ARG;
+  }
+  return BCM_OK;
 }
 
 int bcm_kinetic_energy_noalloc(bcm_plan* P, const void* const u[3], double rho, double g_scale,
