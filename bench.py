@@ -160,6 +160,88 @@ def cpu_baseline(pr, seconds=10.0):
                 oracle_projection_s=t_proj)
 
 
+def next_rows(pr, mesh, args):
+    """The momentum sub-step, the Lagrangian-particle forcing and the checkpoint codec on the
+    same mesh (FP64 fields), each timed with HIP events on the library's stream (timer classes
+    'momentum', 'ib', 'codec') over args.steps calls after one warm-up call."""
+    import numpy as np
+    import torch
+    from bcm_inputs import sphere_particles
+    from paper_1808_04099_amd import Plan
+    m = pr["mesh"]
+    n_cells = m.n_cells
+    plan = Plan(mesh, precision="fp64")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to("cuda")
+    u = [dev(pr["u"][d]) for d in range(3)]
+    out = {}
+
+    def timed(cls, fn):
+        fn()
+        torch.cuda.synchronize()
+        plan.timing_enable(cls)
+        t0 = time.perf_counter()
+        res = [fn() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / args.steps
+        nl, ms = plan.timing_read()
+        plan.timing_enable(None)
+        return res[-1], wall, nl // args.steps, ms / args.steps
+
+    # momentum: Crank-Nicolson with QUICK convection, nu = 1e-3 (Re 300 on the sphere); the
+    # 'momentum' class times the Jacobi sweeps only
+    ut = [plan.empty() for _ in range(3)]
+    mo, wall, nl, ms = timed("momentum", lambda: plan.momentum(
+        u, pr["U_in"], pr["dt"], 1e-3, scheme="cn", cn_tol=1e-10, out=ut))
+    rep = mo["report"]
+    # per Jacobi sweep: read the iterate, u^n (advecting) and the right-hand side, write the
+    # next iterate (3 components each, FP64): 12 words per cell, faces excluded
+    its = rep.n_inner
+    sweep_ms = ms / max(nl, 1)
+    gbs = 96.0 * n_cells / (sweep_ms * 1e-3) / 1e9
+    out["momentum"] = {"scheme": "crank-nicolson + QUICK, nu 1e-3", "ms_per_step": wall,
+                       "iterations": its, "final_rel_res": rep.final_rel_res,
+                       "kernel_launches": nl, "kernel_ms": ms,
+                       "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                                    "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                                    "alg_bytes_per_cell": 96,
+                                    "note": "Jacobi sweep of the Crank-Nicolson system: read "
+                                            "the iterate, u^n and the right-hand side, write "
+                                            "the next iterate (FP64), faces excluded"}}
+    log(f"[bench] momentum: {wall:.2f} ms/step, {its} sweeps, {gbs:.0f} GB/s per launch")
+    # Lagrangian-particle forcing: the sphere's surface at one particle per h^2
+    h = float(m.h().min())
+    X, dV = sphere_particles((0.5, 0.5, 0.5), 0.15, h)
+    Xd, dVd = dev(X), dev(dV)
+    us = [plan.empty() for _ in range(3)]
+    _, wall, nl, ms = timed("ib", lambda: plan.ib_force(u, Xd, pr["dt"], pr["rho"], dV=dVd,
+                                                        out=us))
+    out["ib_particles"] = {"particles": int(len(X)), "ms_per_call": wall, "kernel_ms": ms,
+                           "particles_per_s": len(X) / (ms * 1e-3) if ms > 0 else None,
+                           "note": "27 cells x 3 components gathered and spread per particle "
+                                   "(FP64 atomics); the call also copies u~ to u* and reads "
+                                   "the skip count back"}
+    log(f"[bench] particles: {len(X)} in {ms * 1e3:.1f} us (kernel)")
+    # checkpoint codec on the pressure of the projection step, 1e-4 of max |p|
+    pp = plan.project(u, dev(pr["alpha"]), pr["U_in"], pr["dt"], pr["rho"])["p"]
+    pmax = float(pp.abs().max())
+    step = 2 * 1e-4 * pmax / 24.375
+    buf = torch.empty(plan.compress_bound(), dtype=torch.uint8, device="cuda")
+    s, wall_c, nl_c, ms_c = timed("codec", lambda: plan.compress(pp, step, out=buf))
+    dec = plan.empty(torch.float64)
+    _, wall_d, nl_d, ms_d = timed("codec", lambda: plan.decompress(s, out=dec))
+    err = float((dec - pp).abs().max()) / pmax
+    out["codec"] = {"field": "pressure, FP64", "step": step, "ratio": 8.0 * n_cells / s.numel(),
+                    "max_rel_error": err, "compress_ms": wall_c, "compress_kernel_ms": ms_c,
+                    "decompress_ms": wall_d, "decompress_kernel_ms": ms_d,
+                    "compress_GBps": 8.0 * n_cells / (ms_c * 1e-3) / 1e9,
+                    "decompress_GBps": 8.0 * n_cells / (ms_d * 1e-3) / 1e9}
+    log(f"[bench] codec: ratio 1:{out['codec']['ratio']:.1f}, error {err:.1e}, compress "
+        f"{ms_c:.3f} ms, decompress {ms_d:.3f} ms (kernels)")
+    del buf, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def run(args):
     import numpy as np
     import torch
@@ -287,6 +369,8 @@ def run(args):
         log(f"[bench] fp64: {ms64:.2f} ms/step, {reps64[-1].n_inner} its; "
             f"mixed speed-up {ms64 / ms:.2f}x")
         del p64, o64
+    if args.next_rows and args.workload in ("mixed_channel", "sphere_channel", "small_box"):
+        result["next_rows"] = next_rows(pr, mesh, args)
     if args.copy_probe:
         cp = copy_probe()
         result["copy_probe"] = cp
@@ -317,6 +401,8 @@ def main():
     ap.add_argument("--no-copy-probe", dest="copy_probe", action="store_false",
                     help="skip the device-copy bandwidth probe")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-next-rows", dest="next_rows", action="store_false",
+                    help="skip the momentum / particle / codec measurements")
     ap.add_argument("--opt", action="append", default=[],
                     help="solver option override key=value (e.g. coarse_iters=40)")
     args = ap.parse_args()

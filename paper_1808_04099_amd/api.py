@@ -287,14 +287,18 @@ class Plan:
         _check(st, "bcm_ib_force", allow_warning=False)
         return dict(u_star=us, U_p=Up, F_p=Fp)
 
+    def compress_bound(self):
+        """Worst-case size in bytes of a compressed field of this mesh."""
+        bound = ctypes.c_size_t()
+        _check(self._lib.bcm_compress_bound(self.handle, ctypes.byref(bound)),
+               "bcm_compress_bound", allow_warning=False)
+        return bound.value
+
     def compress(self, field, step, out=None):
         """Wavelet-compress an FP64 cell field; returns the stream as a device uint8 tensor (a
         view of `out` when given, else of a buffer of the worst-case size)."""
         field = self._field(field, "field", torch.float64)
-        bound = ctypes.c_size_t()
-        _check(self._lib.bcm_compress_bound(self.handle, ctypes.byref(bound)),
-               "bcm_compress_bound", allow_warning=False)
-        buf = out if out is not None else torch.empty(bound.value, dtype=torch.uint8,
+        buf = out if out is not None else torch.empty(self.compress_bound(), dtype=torch.uint8,
                                                       device=self.device)
         n = ctypes.c_size_t()
         _check(self._lib.bcm_compress(self.handle, _ptr(field), float(step), _ptr(buf),

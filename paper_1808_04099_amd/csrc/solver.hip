@@ -46,7 +46,8 @@ const char* const kTimerNames[] = {"presmooth16", "presmooth8", "presmooth4", "p
                                    "restrict8", "restrict4", "restrict2", "apply16", "apply8",
                                    "apply4", "apply2", "update", "resid64", "ir", "coarse",
                                    "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
-                                   "export", "xupdate", "momentum", "ib", "codec", nullptr};
+                                   "export", "xupdate", "momentum", "momentum_start", "ib", "codec",
+                                   nullptr};
 
 int level_index(int NL) { return NL == 16 ? 0 : NL == 8 ? 1 : NL == 4 ? 2 : 3; }
 
@@ -767,7 +768,7 @@ int momentum_impl(bcm_plan* P, const bcm_momentum_in* in, bcm_momentum_out* out,
     ea.x[d] = static_cast<const TF*>(in->u[d]);
     ea.xf[d] = P->at<TF>(P->o_mfa[d]);
   }
-  HIPCHK(timed(P, cls_of("momentum", 0), s, [&] { return launch_mom_export<TF>(NL, ea, grid, s); }),
+  HIPCHK(timed(P, cls_of("momentum_start", 0), s, [&] { return launch_mom_export<TF>(NL, ea, grid, s); }),
          "k_mom_export");
   MomArgs<TF> ma{};
   ma.meta = P->at<const CubeMeta>(P->o_meta);
@@ -787,8 +788,10 @@ int momentum_impl(bcm_plan* P, const bcm_momentum_in* in, bcm_momentum_out* out,
   ma.dt = in->dt;
   SolveLog log{rep};
   if (rep) rep->history_len = 0;
-  auto launch = [&](int mode) {
-    return timed(P, cls_of("momentum", 0), s, [&] { return launch_mom<TF>(NL, mode, ma, grid, s); });
+  auto launch = [&](int mode) {  // timer class "momentum": the passes over H (explicit step or
+                                 // Crank-Nicolson sweep); "momentum_start": export and CN start
+    const int cls = cls_of(mode == MOM_CN_START ? "momentum_start" : "momentum", 0);
+    return timed(P, cls, s, [&] { return launch_mom<TF>(NL, mode, ma, grid, s); });
   };
   if (in->scheme != BCM_CN) {
     const bool ab2 = in->scheme == BCM_AB2 && in->h_prev[0];
