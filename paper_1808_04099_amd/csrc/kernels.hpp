@@ -152,12 +152,16 @@ struct ForceArgs {      // u* = (1 - alpha) u~ + alpha u_s; export face-normal c
   double usc[3];
   TF* ustar[3];
   TF* uf;
+  uint8_t* body;        // 16^3 only: per cube 1 if forced (some alpha != 0), else u* = u~ and only
+                        // its faces are written; nullptr = every cube forced and stored
 };
 
 template <typename TF>
 struct DivArgs {        // b = (rho/dt) div(U*)
   Geom g;
   const TF* ustar[3];
+  const TF* u[3];       // u~, read instead of u* in cubes whose body flag is 0
+  const uint8_t* body;  // nullptr: u* everywhere
   const TF* uf;
   double U_in, inv_c;
   double* b;
@@ -170,6 +174,8 @@ struct CorrectArgs {    // u_new = u* - c G_c p; optional face velocities U* - c
   const double* p;
   const double* pf;
   const TF* ustar[3];
+  const TF* u[3];       // u~, read instead of u* in cubes whose body flag is 0 (16^3 kernel)
+  const uint8_t* body;  // nullptr: u* everywhere
   const TF* uf;
   double U_in, c;
   TF* unew[3];

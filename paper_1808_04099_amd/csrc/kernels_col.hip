@@ -954,6 +954,10 @@ __device__ __forceinline__ T face_get(const T* f, int c, int of, int t1, int t2)
 
 // u* = (1 - alpha) u~ + alpha u_s, and the face-normal component of u* on each face.  A pure
 // stream: planes are processed four at a time so that few values are live per lane.
+// With a.body set, only the cubes with some alpha != 0 (body cubes) are forced and stored; the
+// kernel records the flag per cube, and for the other cubes, where u* = u~, it writes only the
+// face slabs of u~ (u_x is read whole for its x faces, u_y two rows per plane, u_z two planes);
+// the divergence and correction kernels then read u~ for them.
 template <typename TF>
 __global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
@@ -961,6 +965,32 @@ __global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
     const int c = a.g.launch[w];
     TF* base = a.uf + (size_t)c * Col<16>::F;
+    if (a.body) {
+      bool any = false;
+      if (a.alpha) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) any = any || ld_nt(a.alpha + (size_t)c * 4096 + k * 256 + t) != TF(0);
+      }
+      any = __syncthreads_or(any);
+      if (t == 0) a.body[c] = any ? 1 : 0;
+      if (!any) {
+        const TF* ux = a.u[0] + (size_t)c * 4096 + t;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const TF v = ld_nt(ux + k * 256);
+          if (i == 0) base[0 * 256 + k * 16 + j] = v;
+          if (i == 15) base[1 * 256 + k * 16 + j] = v;
+        }
+        if (j == 0 || j == 15) {
+          const TF* uy = a.u[1] + (size_t)c * 4096 + t;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) base[(j ? 3 : 2) * 256 + k * 16 + i] = ld_nt(uy + k * 256);
+        }
+        base[4 * 256 + j * 16 + i] = ld_nt(a.u[2] + (size_t)c * 4096 + t);
+        base[5 * 256 + j * 16 + i] = ld_nt(a.u[2] + (size_t)c * 4096 + 15 * 256 + t);
+        continue;
+      }
+    }
 #pragma unroll 1
     for (int k0 = 0; k0 < 16; k0 += 4) {
       TF v[3][4];
@@ -1003,13 +1033,16 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
     const int c = a.g.launch[w];
     const CubeMeta& m = a.g.meta[c];
     const double ih = 1.0 / m.h;
+    const bool forced = !a.body || a.body[c];  // u* stored, else u* = u~
+    const TF* src[3] = {forced ? a.ustar[0] : a.u[0], forced ? a.ustar[1] : a.u[1],
+                        forced ? a.ustar[2] : a.u[2]};
     double acc[16];
     const auto gf = [&](int cc, int of, int aa, int bb) { return face_get(a.uf, cc, of, aa, bb); };
     // z component: neighbours along k are this lane's registers
     {
       TF v[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = ld_nt(a.ustar[2] + (size_t)c * 4096 + k * 256 + t);
+      for (int k = 0; k < 16; ++k) v[k] = ld_nt(src[2] + (size_t)c * 4096 + k * 256 + t);
       double lo, hi;  // face velocities on the -z and +z faces of the column
       {
         const int k4 = m.kind[4], k5 = m.kind[5];
@@ -1031,7 +1064,7 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
       TF v[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        v[k] = ld_nt(a.ustar[d] + (size_t)c * 4096 + k * 256 + t);
+        v[k] = ld_nt(src[d] + (size_t)c * 4096 + k * 256 + t);
         tile[tix16(i, j, k)] = v[k];
       }
 #pragma unroll
@@ -1092,9 +1125,12 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
     // u* of plane k + 1 is loaded while plane k is computed (the loads would otherwise start
     // only after each plane's barrier)
     const size_t g0 = (size_t)c * 4096 + t;
+    const bool forced = !a.body || a.body[c];  // u* stored, else u* = u~
+    const TF* src[3] = {forced ? a.ustar[0] : a.u[0], forced ? a.ustar[1] : a.u[1],
+                        forced ? a.ustar[2] : a.u[2]};
     TF us[3], usn[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) usn[d] = a.unew[d] ? ld_nt(a.ustar[d] + g0) : TF(0);
+    for (int d = 0; d < 3; ++d) usn[d] = a.unew[d] ? ld_nt(src[d] + g0) : TF(0);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       double* b = pl[k & 1];
@@ -1109,7 +1145,7 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
       for (int d = 0; d < 3; ++d) us[d] = usn[d];
       if (k < 15) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) usn[d] = a.unew[d] ? ld_nt(a.ustar[d] + g0 + (k + 1) * 256) : TF(0);
+        for (int d = 0; d < 3; ++d) usn[d] = a.unew[d] ? ld_nt(src[d] + g0 + (k + 1) * 256) : TF(0);
       }
       __syncthreads();
       const size_t g = g0 + k * 256;

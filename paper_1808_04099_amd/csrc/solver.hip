@@ -92,6 +92,7 @@ struct bcm_plan {
   bool ib = false;
   size_t o_cflag = 0;  // wavelet codec: total bytes (u64) and error flags (u32)
   size_t o_ustar[3] = {0, 0, 0}, o_uf = 0, o_b64 = 0, o_pf = 0, o_lam = 0;
+  size_t o_body = 0;  // per-cube forcing flags of the 16^3 projection (1 byte per cube)
   size_t o_r = 0, o_z = 0, o_p = 0, o_q = 0, o_d = 0;
   size_t o_zf[2] = {0, 0}, o_pfk[2] = {0, 0};
   std::vector<size_t> o_x, o_b, o_xf[2];  // per level (index 0 unused for x/b: level 0 = z/r)
@@ -629,12 +630,25 @@ int project_impl(bcm_plan* P, const bcm_project_in* in, bcm_project_out* out, bc
     fa.ustar[d] = P->at<TF>(P->o_ustar[d]);
   }
   fa.uf = P->at<TF>(P->o_uf);
+  // 16^3 kernels: force and store u* only in cubes that hold some alpha != 0; the others pass
+  // u~ on (the face-velocity output needs the generic correction, which reads u* everywhere)
+  const bool sel = NL == 16 && !out->face_u[0] && !out->face_u[1] && !out->face_u[2];
+  fa.body = sel ? P->at<uint8_t>(P->o_body) : nullptr;
   HIPCHK(timed(P, cls_of("force", 0), s, [&] { return launch_force<TF>(NL, fa, s); }), "k_force");
   double* p = out->p;
   int st = BCM_OK;
   if (!p_given) {
-    DivArgs<TF> da{geom(P, NL), {fa.ustar[0], fa.ustar[1], fa.ustar[2]}, fa.uf, in->U_in, 1.0 / c,
-                   P->at<double>(P->o_b64), nullptr};
+    DivArgs<TF> da{};
+    da.g = geom(P, NL);
+    for (int d = 0; d < 3; ++d) {
+      da.ustar[d] = fa.ustar[d];
+      da.u[d] = fa.u[d];
+    }
+    da.body = fa.body;
+    da.uf = fa.uf;
+    da.U_in = in->U_in;
+    da.inv_c = 1.0 / c;
+    da.b = P->at<double>(P->o_b64);
     HIPCHK(timed(P, cls_of("div", 0), s, [&] { return launch_div<TF>(NL, da, s); }), "k_div");
     bool guess = false;
     if (in->p0) {
@@ -658,10 +672,12 @@ int project_impl(bcm_plan* P, const bcm_project_in* in, bcm_project_out* out, bc
   ca.pf = P->at<const double>(P->o_pf);
   for (int d = 0; d < 3; ++d) {
     ca.ustar[d] = fa.ustar[d];
+    ca.u[d] = fa.u[d];
     ca.unew[d] = static_cast<TF*>(out->u_new[d]);
     ca.face_u[d] = static_cast<TF*>(out->face_u[d]);
   }
   ca.uf = fa.uf;
+  ca.body = fa.body;
   ca.U_in = in->U_in;
   ca.c = c;
   HIPCHK(timed(P, cls_of("correct", 0), s, [&] { return launch_correct<TF>(NL, ca, s); }), "k_correct");
@@ -1139,6 +1155,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   P->o_cw = take(top, 4 * nc * sizeof(double));
   for (int d = 0; d < 3; ++d) P->o_ustar[d] = take(top, cells * Tf);
   P->o_uf = take(top, size_t(face_stride(M.n)) * nc * Tf);
+  P->o_body = take(top, nc);
   P->o_b64 = take(top, cells * 8);
   P->o_pf = take(top, size_t(face_stride(M.n)) * nc * 8);
   P->o_lam = take(top, cells * 8);
