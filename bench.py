@@ -28,20 +28,43 @@ PEAK_HBM_GBS = 8000.0
 
 # Algorithmic bytes per fine-level cell of one launch (halo / face traffic excluded), by
 # timer class, for inner precision size s (4 for mixed, 8 for fp64) and field size f.
-def alg_bytes_per_cell(cls, s, f):
+def alg_bytes_per_cell(cls, s, f, body=1.0):
+    """Algorithmic bytes per cell of the class's level (face buffers excluded), or None for
+    classes that are not a streaming pass (the cube-graph solve, the scalar finalize).
+    s, f: bytes per solver value and per field value; body: the fraction of cubes that hold
+    some nonzero volume fraction (the only ones the 16^3 forcing kernel reads and stores)."""
     return {
         "presmooth16": 2 * s + s / 8,    # read b; write x and the restricted residual
+        "presmooth8": 3 * s + s / 8,     # below the finest level b is completed (its cross-cube
+        "presmooth4": 3 * s + s / 8,     # terms) and written back as well
+        "presmooth2": 3 * s + s / 8,
         "postsmooth16": 4 * s + s / 8,   # read x, b, q, coarse correction; write x
-        "restrict16": s / 4,             # the restricted residual's cross-cube terms: read, write
+        "postsmooth8": 3 * s + s / 8,    # read x, b, coarse correction; write x
+        "postsmooth4": 3 * s + s / 8,
+        "postsmooth2": 3 * s + s / 8,
+        "restrict2": s / 4,              # the one-cell-per-cube residual's cross-cube terms
         "apply16": 4 * s,                # read z, p; write p, q
         "update": 3 * s,                 # read r, q; write r
         "xupdate": 3 * s,                # read x, p; write x (beside the next V-cycle)
         "resid64": 16 + s,               # read p, b (FP64); write r
         "ir": 8 + s + 8,                 # read p, d; write p
-        "force": 7 * f,                  # read u~ (3), alpha; write u* (3)
+        "force": f + 6 * f * body,       # read alpha; in body cubes read u~ (3), write u* (3)
         "div": 3 * f + 8,                # read u* (3); write b
         "correct": 8 + 6 * f,            # read p, u* (3); write u_new (3)
-    }[cls]
+    }.get(cls)
+
+
+def level_cells(cls, n_cells, n):
+    """Cells of the per-cube level a class runs on (the trailing edge length in its name)."""
+    digits = "".join(ch for ch in cls if ch.isdigit())
+    if cls in ("resid64",) or not digits:
+        return n_cells
+    return n_cells * (int(digits) / n) ** 3
+
+
+CLASSES = ("presmooth16", "postsmooth16", "apply16", "update", "xupdate", "resid64", "ir",
+           "coarse", "force", "div", "correct", "presmooth8", "postsmooth8", "presmooth4",
+           "postsmooth4", "presmooth2", "postsmooth2", "restrict2", "finalize")
 
 
 def log(msg):
@@ -270,9 +293,9 @@ def run(args):
     def step(plan, u, a, out):
         return plan.project(u, a, pr["U_in"], pr["dt"], pr["rho"], out=out)["report"]
 
-    def timed_steps(plan, u, a, out, steps, timer_cls=None):
+    def timed_steps(plan, u, a, out, steps, timer_cls=None, every=1):
         if timer_cls:
-            plan.timing_enable(timer_cls)
+            plan.timing_enable(timer_cls, every)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         reps = [step(plan, u, a, out) for _ in range(steps)]
@@ -287,34 +310,37 @@ def run(args):
     plan, u, a, out = make(prec)
     s = 4 if prec != "fp64" else 8
     f = 4 if prec == "mixed_f32fields" else 8
+    body = float((a.view(m.n_cubes, -1) != 0).any(dim=1).double().mean().item())
     for _ in range(args.warmup):
         rep = step(plan, u, a, out)
     torch.cuda.synchronize()
     # time each kernel class over two untimed steps (one class timed per step); the dominant
-    # one is the class with the largest share of the step
+    # one is the streaming class with the largest share of the step
     dominant, best = args.kernel, -1.0
     class_ms = {}
-    for cls in () if args.kernel else ("presmooth16", "postsmooth16", "restrict16", "apply16",
-                                       "update", "xupdate", "resid64", "ir", "coarse", "force",
-                                       "div", "correct"):
+    for cls in () if args.kernel else CLASSES:
         _, _, (nl, tot) = timed_steps(plan, u, a, out, 2, cls)
         nl, tot = nl // 2, tot / 2.0       # per step
         class_ms[cls] = {"launches": nl, "ms_per_step": tot}
-        if cls != "coarse" and nl > 0:
-            gbs = alg_bytes_per_cell(cls, s, f) * n_cells / (tot / nl * 1e-3) / 1e9
+        bpc = alg_bytes_per_cell(cls, s, f, body)
+        if bpc is not None and nl > 0:
+            gbs = bpc * level_cells(cls, n_cells, m.n) / (tot / nl * 1e-3) / 1e9
             class_ms[cls].update(alg_gbs=gbs, frac=gbs / PEAK_HBM_GBS)
         log(f"[bench] {cls}: {nl} launches, {tot:.3f} ms per step")
-        if args.kernel is None and cls != "coarse" and tot > best:
+        if args.kernel is None and bpc is not None and tot > best:
             dominant, best = cls, tot
-    ms, reps, (nl, tot) = timed_steps(plan, u, a, out, args.steps, dominant)
+    # in the timed steps one launch of the dominant class in four is bracketed by events
+    # (each event holds the stream for a few microseconds)
+    ms, reps, (nl, tot) = timed_steps(plan, u, a, out, args.steps, dominant, every=4)
     rep = reps[-1]
     sweeps = plan.opts.pre_sweeps + plan.opts.post_sweeps
     per_iter = sweeps + 2              # smoothing sweeps + restriction residual + operator apply
     updates = n_cells * (rep.n_inner * per_iter + (rep.n_outer + 1) + 2)
     value = updates / (ms * 1e-3)
     avg_ms = tot / max(nl, 1)
-    bpc = alg_bytes_per_cell(dominant, s, f)
-    achieved = bpc * n_cells / (avg_ms * 1e-3) / 1e9
+    bpc = alg_bytes_per_cell(dominant, s, f, body)
+    cells_dom = level_cells(dominant, n_cells, m.n)
+    achieved = bpc * cells_dom / (avg_ms * 1e-3) / 1e9
     log(f"[bench] {prec}: {ms:.2f} ms/step, {rep.n_inner} inner its, {rep.n_outer} outer, "
         f"rel.res {rep.final_rel_res:.2e}; {dominant}: {avg_ms:.3f} ms/launch, "
         f"{achieved:.0f} GB/s")
@@ -340,7 +366,7 @@ def run(args):
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(dominant, args.workload, prec),
-                     "alg_bytes_per_launch": bpc * n_cells, "alg_bytes_per_cell": bpc,
+                     "alg_bytes_per_launch": bpc * cells_dom, "alg_bytes_per_cell": bpc,
                      "launches": nl, "avg_launch_ms": avg_ms},
         "kernel_classes": class_ms,
     }
@@ -393,8 +419,7 @@ def main():
                     choices=["mixed_channel", "sphere_channel", "small_box", "multilevel"])
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "mixed_f32fields"])
     ap.add_argument("--kernel", default=None,
-                    choices=["presmooth16", "postsmooth16", "restrict16", "apply16", "update",
-                             "xupdate", "resid64", "ir", "force", "div", "correct"],
+                    choices=[c for c in CLASSES if alg_bytes_per_cell(c, 4, 8) is not None],
                     help="timer class for the roofline (skips the per-class survey)")
     ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")

@@ -380,8 +380,13 @@ int bcm_apply_laplacian(bcm_plan* plan, const double* d_p, double* d_Ap, void* s
 /* Kernel timing: when enabled, every launch of the named kernel class is bracketed by HIP
  * events on the launch stream; bcm_timing_read returns the number of timed launches and
  * their summed duration (milliseconds), synchronising the events.  Classes are listed by
- * bcm_timing_name(i) for i = 0.. until it returns NULL. */
+ * bcm_timing_name(i) for i = 0.. until it returns NULL.
+ * The events themselves hold the stream for a few microseconds on each side of a timed
+ * launch; bcm_timing_sample(plan, every) (every >= 1; 1 after bcm_timing_enable) times only
+ * the first launch of each run of `every` launches of the class, to keep that cost out of a
+ * timed region. */
 int bcm_timing_enable(bcm_plan* plan, const char* kernel_class);
+int bcm_timing_sample(bcm_plan* plan, int32_t every);
 int bcm_timing_read(bcm_plan* plan, int64_t* launches, double* total_ms);
 const char* bcm_timing_name(int i);
 

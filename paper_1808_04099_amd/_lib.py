@@ -102,6 +102,7 @@ EXPORTS = {
     "bcm_kinetic_energy_noalloc": (c_int, [c_void_p, POINTER(c_void_p), c_double, c_double,
                                            POINTER(c_double), POINTER(c_void_p), c_void_p]),
     "bcm_timing_enable": (c_int, [c_void_p, c_char_p]),
+    "bcm_timing_sample": (c_int, [c_void_p, c_int32]),
     "bcm_timing_read": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_double)]),
     "bcm_timing_name": (c_char_p, [c_int]),
     "bcm_mesh_cells": (c_int64, [c_void_p]),

@@ -344,10 +344,16 @@ class Plan:
                "bcm_apply_laplacian", allow_warning=False)
         return out
 
-    def timing_enable(self, kernel_class):
+    def timing_enable(self, kernel_class, every=1):
+        """Time launches of a kernel class with HIP events (None: off); every > 1 times only
+        one launch in each run of `every`, which keeps the events' own stream stalls out of
+        the rest of a timed region."""
         _check(self._lib.bcm_timing_enable(
             self.handle, kernel_class.encode() if kernel_class else None),
             "bcm_timing_enable", allow_warning=False)
+        if kernel_class and every != 1:
+            _check(self._lib.bcm_timing_sample(self.handle, int(every)),
+                   "bcm_timing_sample", allow_warning=False)
 
     def timing_read(self):
         n = ctypes.c_int64()

@@ -48,6 +48,12 @@ struct SmoothArgs {
   int sweeps, black_first, zero_init;
   T* bc;                // pre-smoother: restricted residual with the cross-cube terms left out
                         // (completed by the face correction), or nullptr
+  const T* rfx;         // pre-smoother below the finest level: faces of the finer level's
+                        // pre-smoothed iterate; b then lacks its cross-cube terms, which the
+                        // launch adds first and stores back into b_fixed (= b).  nullptr: b is
+                        // complete
+  T* b_fixed;
+  double rfx_hscale;    // cell width of the finer level = meta.h * rfx_hscale
   const T* r_dot;       // fused <x, r_dot>_V and <x, q_dot>_V (level 0 of a Krylov step)
   const T* q_dot;
   double* part_zr;

@@ -410,7 +410,11 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
   // sweep form (same update order): shifted columns before restriction; with the trilinear
   // prolongation the paired form in FP32 (fewer registers), else the masked form
   constexpr int SWEEP = !POST ? 2 : (TRI && sizeof(T) == 4 ? 1 : 0);
+  // pre-smoother below the finest level: the finer level's face correction is applied here
+  constexpr bool RFX = !POST && NL < 16;
+  constexpr int NF = RFX ? 2 * NL : NL;  // the finer level
   __shared__ T tile[C::CPB * C::TS];
+  __shared__ T hsum[RFX ? C::CPB * 6 * C::N2 : 1];  // per cube and face: 2x2 sums of halo values
   __shared__ T ctile[TRI ? C::CPB * Pro<NL>::P3 : 1];
   __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
   __shared__ uint32_t cdesc[TRI && PF ? ProPF<NL>::NT : 1];
@@ -423,12 +427,38 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
   const bool dots = POST && a.part_zr != nullptr;
   T nx[NL], nb[NL], nxc[C::H], rf[6], rc[6];
   int kinds[6];
+  // face correction: raw finer-level halo values of the four finer cells (t1, t2) =
+  // (2i + q % 2, 2j + q / 2) behind this column's position on each face
+  T rr[RFX ? 24 : 1];
+  int rk[RFX ? 6 : 1];
+  const bool rfx = RFX && a.rfx != nullptr;
   auto fetch = [&](int cc) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
       nb[k] = ld_nt(a.b + g);
       if (POST) nx[k] = ld_nt(a.x + g);
+    }
+    if constexpr (RFX) {
+      if (rfx) {
+        // the slot of (2i, 2j); the other three lie 1 and NF apart on a same-level face (or
+        // the cube's own slab), 1 and NL apart among a finer neighbour's 2x2 means, and share
+        // the coarser neighbour's value
+        Slots S;
+        slots<NF, ML>(a.g.meta[cc], cc, 2 * i, 2 * j, S);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int kd = S.kind[f];
+          const int d1 = ML && kd == FK_COARSER ? 0 : 1;
+          const int d2 = ML && kd == FK_COARSER ? 0 : (ML && kd == FK_FINER ? NL : NF);
+          const T* p = a.rfx + S.fine[f];
+          rr[4 * f] = p[0];
+          rr[4 * f + 1] = p[d1];
+          rr[4 * f + 2] = p[d2];
+          rr[4 * f + 3] = p[d1 + d2];
+          rk[f] = kd;
+        }
+      }
     }
     if (POST) {
       if (!TRI) {
@@ -497,6 +527,17 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
 #pragma unroll
       for (int f = 0; f < 4; ++f) tile[C::halo(L.s, f, i, j)] = T(0);
     }
+    if constexpr (RFX) {
+      if (rfx) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int kd = rk[f];
+          hsum[(L.s * 6 + f) * C::N2 + j * NL + i] =
+              (halo_val<T>(kd, rr[4 * f]) + halo_val<T>(kd, rr[4 * f + 1])) +
+              (halo_val<T>(kd, rr[4 * f + 2]) + halo_val<T>(kd, rr[4 * f + 3]));
+        }
+      }
+    }
     const T h = T(m.h * a.g.hscale);
     const T h2 = h * h;
     T d0, dm, dl;
@@ -506,6 +547,27 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
     __syncthreads();
+    if constexpr (RFX) {
+      // the finer level's restriction lacked the cross-cube terms of its residual: for each
+      // face the cell lies on (x, y, then z), -(1/8) of the sum of its 2x2 finer halo values
+      // over h_fine^2
+      if (rfx) {
+        const T hf = T(m.h * a.rfx_hscale);
+        const T sc = T(0.125) / (hf * hf);
+        const T* hs = hsum + L.s * 6 * C::N2;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+          T corr = T(0);
+          if (i == 0) corr += hs[0 * C::N2 + k * NL + j];
+          if (i == NL - 1) corr += hs[1 * C::N2 + k * NL + j];
+          if (j == 0) corr += hs[2 * C::N2 + k * NL + i];
+          if (j == NL - 1) corr += hs[3 * C::N2 + k * NL + i];
+          if (k == 0) corr += hs[4 * C::N2 + j * NL + i];
+          if (k == NL - 1) corr += hs[5 * C::N2 + j * NL + i];
+          bv[k] = bv[k] - corr * sc;
+        }
+      }
+    }
     if (PF && un < U) {
       if (TRI) {
         coarse_val<NL, T>(a.xc, cdesc, cent, cvn, sgn);
@@ -604,6 +666,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
         st_nt(a.x + (size_t)c * C::N3 + k * C::N2 + L.l, x[k]);
+        if (rfx) st_nt(a.b_fixed + (size_t)c * C::N3 + k * C::N2 + L.l, bv[k]);
         if (dots) {
           zr += vol * double(x[k]) * double(bv[k]);
           if (a.q_dot) zq += vol * double(x[k]) * double(q[k]);
@@ -657,9 +720,11 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
   }
 }
 
-// Completes the restriction fused into the pre-smoother.  A coarse cell on a cube's boundary
-// still lacks the cross-cube terms of its children's residuals, -(1/8) sum nbeff x_nb / h^2
-// over the children's faces that border a neighbour.  Lane (i, j) of each cube slot gathers
+// Completes the restriction fused into the pre-smoother of the last per-cube level (the
+// pre-smoothers of the levels in between apply the same correction to their own right-hand
+// side as they load it).  A coarse cell on a cube's boundary still lacks the cross-cube terms
+// of its children's residuals, -(1/8) sum nbeff x_nb / h^2 over the children's faces that
+// border a neighbour.  Lane (i, j) of each cube slot gathers
 // the six halo values at tangential (t1, t2) = (i, j) (as the smoothers do), the 2x2 children
 // of each coarse face cell are summed in LDS, and each coarse boundary cell adds the sums of
 // its faces in the order x, y, z.

@@ -60,6 +60,8 @@ struct Status {
 
 struct Timer {
   int cls = -1;
+  int every = 1;     // time one launch of the class in every `every`
+  int64_t seen = 0;  // launches of the class since enabled
   std::vector<hipEvent_t> ev;
   size_t used = 0;
 };
@@ -141,7 +143,7 @@ int hip_fail(hipError_t e, const char* what) {
 template <class F>
 hipError_t timed(bcm_plan* P, int cls, hipStream_t s, F&& launch) {
   Timer& t = P->timer;
-  const bool on = t.cls == cls;
+  const bool on = t.cls == cls && t.seen++ % t.every == 0;
   if (on) {
     if (t.used + 2 > t.ev.size()) {
       for (int i = 0; i < 256; ++i) {
@@ -268,6 +270,41 @@ int coarse_split(bcm_plan* P, const T* b_in, T* x_out, T* xf_out, hipStream_t s)
   return st;
 }
 
+// The V-cycle's arrays: iterate, right-hand side and the two face buffers of level l.
+template <typename T>
+struct VLevels {
+  bcm_plan* P;
+  T* X(int l) const { return l == 0 ? P->at<T>(P->o_z) : P->at<T>(P->o_x[l]); }
+  T* B(int l) const { return l == 0 ? P->at<T>(P->o_r) : P->at<T>(P->o_b[l]); }
+  T* F(int ab, int l) const { return l == 0 ? P->at<T>(P->o_zf[ab]) : P->at<T>(P->o_xf[ab][l]); }
+};
+
+// The pre-smoother of level l (< nlev - 1): from zero, with the restriction of its residual
+// fused in.  Its cross-cube terms need the neighbours' smoothed faces, so the next level's
+// pre-smoother adds them (it reads nothing across faces itself: its iterate starts at zero),
+// and kc_rfix only after the last such level.
+template <typename T>
+int presmooth(bcm_plan* P, int l, hipStream_t s) {
+  const VLevels<T> V{P};
+  const int NL = P->n >> l;
+  SmoothArgs<T> sa{};
+  sa.g = geom(P, NL);
+  sa.x = V.X(l);
+  sa.b = V.B(l);
+  sa.xf_out = V.F(0, l);
+  sa.sweeps = P->o.pre_sweeps;
+  sa.black_first = 0;
+  sa.zero_init = 1;
+  sa.bc = V.B(l + 1);
+  if (l > 0) {
+    sa.rfx = V.F(0, l - 1);
+    sa.b_fixed = V.B(l);
+    sa.rfx_hscale = geom(P, NL * 2).hscale;
+  }
+  HIPCHK(timed(P, cls_of("presmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "kc_smooth (pre)");
+  return BCM_OK;
+}
+
 // One V-cycle on (b_0 = r, x_0 = z): per-cube levels NL = n, n/2, ..., 2 smoothed with
 // red-black Gauss-Seidel, then the one-cell-per-cube level (cube-graph multigrid, or the
 // paper's CG with coarse_solver 0).  At level 0 the final smoothing also accumulates <z, r>
@@ -275,24 +312,18 @@ int coarse_split(bcm_plan* P, const T* b_in, T* x_out, T* xf_out, hipStream_t s)
 template <typename T, class Hook>
 int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s, Hook&& before_coarse) {
   const int L = P->nlev;
-  auto X = [&](int l) { return l == 0 ? P->at<T>(P->o_z) : P->at<T>(P->o_x[l]); };
-  auto B = [&](int l) { return l == 0 ? P->at<T>(P->o_r) : P->at<T>(P->o_b[l]); };
-  auto F = [&](int ab, int l) { return l == 0 ? P->at<T>(P->o_zf[ab]) : P->at<T>(P->o_xf[ab][l]); };
+  const VLevels<T> V{P};
+  auto X = [&](int l) { return V.X(l); };
+  auto B = [&](int l) { return V.B(l); };
+  auto F = [&](int ab, int l) { return V.F(ab, l); };
   const bcm_solver_opts& o = P->o;
   for (int l = 0; l < L - 1; ++l) {
     const int NL = P->n >> l;
-    SmoothArgs<T> sa{};
-    sa.g = geom(P, NL);
-    sa.x = X(l);
-    sa.b = B(l);
-    sa.xf_out = F(0, l);
-    sa.sweeps = o.pre_sweeps;
-    sa.black_first = 0;
-    sa.zero_init = 1;
-    sa.bc = B(l + 1);  // restriction fused into the pre-smoother, completed by kc_rfix
-    HIPCHK(timed(P, cls_of("presmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "kc_smooth (pre)");
-    RestrictFixArgs<T> ra{geom(P, NL), F(0, l), B(l + 1)};
-    HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launchc_rfix<T>(NL, ra, s); }), "kc_rfix");
+    if (const int st = presmooth<T>(P, l, s)) return st;
+    if (l == L - 2) {
+      RestrictFixArgs<T> ra{geom(P, NL), F(0, l), B(l + 1)};
+      HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launchc_rfix<T>(NL, ra, s); }), "kc_rfix");
+    }
   }
   if (P->graph && P->g_split > 0) {
     if (const int st = before_coarse(nullptr)) return st;
@@ -1657,6 +1688,8 @@ int bcm_timing_enable(bcm_plan* P, const char* name) {
   }
   P->timer.used = 0;
   P->timer.cls = -1;
+  P->timer.every = 1;
+  P->timer.seen = 0;
   if (!name || !*name) return BCM_OK;
   for (int i = 0; kTimerNames[i]; ++i)
     if (!std::strcmp(kTimerNames[i], name)) {
@@ -1665,6 +1698,16 @@ int bcm_timing_enable(bcm_plan* P, const char* name) {
     }
   set_error(std::string("bcm_timing_enable: unknown kernel class ") + name);
   return BCM_ERR_INVALID_ARG;
+}
+
+int bcm_timing_sample(bcm_plan* P, int32_t every) {
+  if (!P || every < 1) {
+    set_error("bcm_timing_sample: NULL plan or every < 1");
+    return BCM_ERR_INVALID_ARG;
+  }
+  P->timer.every = every;
+  P->timer.seen = 0;
+  return BCM_OK;
 }
 
 int bcm_timing_read(bcm_plan* P, int64_t* launches, double* total_ms) {

@@ -88,3 +88,19 @@ def test_unreachable_tolerance_stagnates(precision):
     assert rep.n_inner < 100 and rep.n_outer < 20
     assert rep.final_rel_res <= 1e-13
     _check_report(m, b, p, rep)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sampled_kernel_timing(precision):
+    """bcm_timing_sample(every): one launch in each run of `every` is timed.  The r update runs
+    once per Krylov iteration, so ceil(n_inner / every) of its launches carry events."""
+    m, b = _problem()
+    plan = plan_for(m, precision, tol=1e-10)
+    for every in (1, 3):
+        plan.timing_enable("update", every)
+        p, rep = plan.poisson_solve(dev(b))
+        n, ms = plan.timing_read()
+        plan.timing_enable(None)
+        log(f"  {precision}: every {every}: {n} timed of {rep.n_inner} launches, {ms:.3f} ms")
+        assert rep.status == OK
+        assert n == -(-rep.n_inner // every) and ms > 0.0
