@@ -1031,28 +1031,36 @@ __global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
     const int c = a.g.launch[w];
     TF* base = a.uf + (size_t)c * Col<16>::F;
     if (a.body) {
-      bool any = false;
-      if (a.alpha) {
+      // alpha and the face sources of u~ are loaded together, before the decision; all three
+      // comparisons wait only on loads issued before them
+      const size_t g0 = (size_t)c * 4096 + t;
+      const bool ry = j == 0 || j == 15;
+      const TF* ap = a.alpha ? a.alpha : a.u[0];  // no alpha: loads that decide nothing
+      const TF* yp = a.u[1] + (ry ? g0 : (size_t)c * 4096 + (t & 15));  // row j = 0 otherwise
+      TF al[16], ux[16], uy[16], uz[2];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) any = any || ld_nt(a.alpha + (size_t)c * 4096 + k * 256 + t) != TF(0);
+      for (int k = 0; k < 16; ++k) {
+        al[k] = ld_nt(ap + g0 + k * 256);
+        ux[k] = ld_nt(a.u[0] + g0 + k * 256);
+        uy[k] = ld_nt(yp + k * 256);
       }
-      any = __syncthreads_or(any);
+      uz[0] = ld_nt(a.u[2] + g0);
+      uz[1] = ld_nt(a.u[2] + g0 + 15 * 256);
+      bool nz = false;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) nz |= al[k] != TF(0);
+      nz = nz && a.alpha != nullptr;
+      const bool any = __syncthreads_or(nz);
       if (t == 0) a.body[c] = any ? 1 : 0;
       if (!any) {
-        const TF* ux = a.u[0] + (size_t)c * 4096 + t;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-          const TF v = ld_nt(ux + k * 256);
-          if (i == 0) base[0 * 256 + k * 16 + j] = v;
-          if (i == 15) base[1 * 256 + k * 16 + j] = v;
+          if (i == 0) base[0 * 256 + k * 16 + j] = ux[k];
+          if (i == 15) base[1 * 256 + k * 16 + j] = ux[k];
+          if (ry) base[(j ? 3 : 2) * 256 + k * 16 + i] = uy[k];
         }
-        if (j == 0 || j == 15) {
-          const TF* uy = a.u[1] + (size_t)c * 4096 + t;
-#pragma unroll
-          for (int k = 0; k < 16; ++k) base[(j ? 3 : 2) * 256 + k * 16 + i] = ld_nt(uy + k * 256);
-        }
-        base[4 * 256 + j * 16 + i] = ld_nt(a.u[2] + (size_t)c * 4096 + t);
-        base[5 * 256 + j * 16 + i] = ld_nt(a.u[2] + (size_t)c * 4096 + 15 * 256 + t);
+        base[4 * 256 + j * 16 + i] = uz[0];
+        base[5 * 256 + j * 16 + i] = uz[1];
         continue;
       }
     }
