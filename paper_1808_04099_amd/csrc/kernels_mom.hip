@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
     const int ridx1 = rd == 0 ? (i + 2) * M::W4 + rpos1 : rpos1 * M::W4 + i + 2;
     const int rp = rside ? NL + 1 : 0;
     const int ria = rd == 0 ? (i + 1) * M::W2 + rp : rp * M::W2 + i + 1;
-    const Affine ra = rr[rd];
+    const Affine ra = rd == 0 ? rr[0] : rr[1];  // a select: a dynamic index would put rr in scratch
 #pragma unroll 1
     for (int k = 0; k < NL; ++k) {
       const double axk = double(a.a[0][cb + k * M::N2]), ayk = double(a.a[1][cb + k * M::N2]);
