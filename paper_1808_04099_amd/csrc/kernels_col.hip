@@ -68,7 +68,7 @@ template <int NL>
 __device__ __forceinline__ int unit_cube(const Geom& g, int u, int s) {
   constexpr int CPB = Col<NL>::CPB;
   const int p = CPB == 1 ? u : ((u >> 3) * CPB + s) * 8 + (u & 7);
-  int c = p < g.n_cubes ? g.launch[p] : -1;
+  int c = p < g.n_cubes ? ro_load(g.launch, p) : -1;
   if (Col<NL>::N2 >= 64) c = __builtin_amdgcn_readfirstlane(c);  // one cube per wavefront
   return c;
 }
@@ -87,8 +87,8 @@ struct Slots {
 };
 
 // ML = false: a single-level mesh (only same-level neighbours and domain boundaries).
-template <int NL, bool ML>
-__device__ __forceinline__ void slots(const CubeMeta& m, int self, int t1, int t2, Slots& S) {
+template <int NL, bool ML, class MT>
+__device__ __forceinline__ void slots(const MT& m, int self, int t1, int t2, Slots& S) {
   using C = Col<NL>;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -134,8 +134,8 @@ __device__ __forceinline__ void stage(T* tile, const T (&hv)[6], const LaneC<NL>
 }
 
 // Diagonal (sum of own coefficients) of the lane's column: cells k = 0, 1..NL-2, NL-1.
-template <int NL, typename T>
-__device__ __forceinline__ void diag(const CubeMeta& m, int i, int j, T& d0, T& dm, T& dl) {
+template <int NL, typename T, class MT>
+__device__ __forceinline__ void diag(const MT& m, int i, int j, T& d0, T& dm, T& dl) {
   T c = T(6);
   if (i == 0) c += T(RuleTab<RULE_P>::own(m.kind[0])) - T(1);
   if (i == NL - 1) c += T(RuleTab<RULE_P>::own(m.kind[1])) - T(1);
@@ -170,8 +170,8 @@ __device__ __forceinline__ void export_col(T* xf, int c, const T (&x)[NL], int i
 // 2x2 means of the face slabs on faces that border a coarser cube (see face_stride), from the
 // cube's values in the LDS tile; summed in the order (0,0), (1,0), (0,1), (1,1) of the two
 // tangential axes.  Lanes of each cube slot with l < (NL/2)^2 compute one mean per face.
-template <int NL, typename T>
-__device__ __forceinline__ void export_avg(T* xf, int c, const T* tile, const CubeMeta& m,
+template <int NL, typename T, class MT>
+__device__ __forceinline__ void export_avg(T* xf, int c, const T* tile, const MT& m,
                                            const LaneC<NL>& L) {
   using C = Col<NL>;
   if (L.l >= C::H2) return;
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
         // the cube's own slab), 1 and NL apart among a finer neighbour's 2x2 means, and share
         // the coarser neighbour's value
         Slots S;
-        slots<NF, ML>(a.g.meta[cc], cc, 2 * i, 2 * j, S);
+        slots<NF, ML>(meta_ro(a.g.meta, cc), cc, 2 * i, 2 * j, S);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
           const int kd = S.kind[f];
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
           nxc[kk] = a.xc[(size_t)cc * C::H3 + (kk * C::H + (j >> 1)) * C::H + (i >> 1)];
       }
       Slots S;
-      slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
+      slots<NL, ML>(meta_ro(a.g.meta, cc), cc, i, j, S);
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
         kinds[f] = S.kind[f];
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothA
     if (!PF) fetch(ce);  // FP64 at 16^3: no prefetch (registers go to occupancy)
     T x[NL], bv[NL];
     T zlo = T(0), zhi = T(0);
-    const CubeMeta& m = a.g.meta[ce];
+    MetaRO& m = meta_ro(a.g.meta, ce);
     T eh[6];
     if (TRI) {
       if (PF) {
@@ -743,7 +743,7 @@ __global__ __launch_bounds__(256) void kc_rfix(RestrictFixArgs<T> a) {
   auto fetch = [&](int uu) {
     const int c = unit_cube<NL>(a.g, uu, L.s);
     Slots S;
-    slots<NL, ML>(a.g.meta[c < 0 ? 0 : c], c < 0 ? 0 : c, L.i, L.j, S);
+    slots<NL, ML>(meta_ro(a.g.meta, c < 0 ? 0 : c), c < 0 ? 0 : c, L.i, L.j, S);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       kinds[f] = c < 0 ? FK_OUTFLOW : S.kind[f];
@@ -793,7 +793,7 @@ __global__ __launch_bounds__(256) void kc_rfix(RestrictFixArgs<T> a) {
         const T* h = hv + (s2 * 6 + f) * C::N2 + (2 * T2) * NL + 2 * T1;
         corr += (h[0] + h[1]) + (h[NL] + h[NL + 1]);
       }
-      const T hh = T(a.g.meta[cg[n] / C::H3].h * a.g.hscale);
+      const T hh = T(meta_ro(a.g.meta, cg[n] / C::H3).h * a.g.hscale);
       a.bc[cg[n]] = cb[n] - corr * (T(0.125) / (hh * hh));
     }
     __syncthreads();  // hv is rewritten for the next unit
@@ -823,7 +823,7 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
       np[k] = a.first ? T(0) : ld_nt(a.p + g);
     }
     Slots S;
-    slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
+    slots<NL, ML>(meta_ro(a.g.meta, cc), cc, i, j, S);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       kinds[f] = S.kind[f];
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
     if (!PF) fetch(ce);  // FP64 at 16^3: no prefetch (registers go to occupancy)
     T x[NL], hv[6];
     T zlo, zhi;
-    const CubeMeta& m = a.g.meta[ce];
+    MetaRO& m = meta_ro(a.g.meta, ce);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       x[k] = nz[k] + beta * np[k];
@@ -905,7 +905,7 @@ __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
       nb[k] = a.b ? ld_nt(a.b + g) : 0.0;
     }
     Slots S;
-    slots<NL, ML>(a.g.meta[cc], cc, i, j, S);
+    slots<NL, ML>(meta_ro(a.g.meta, cc), cc, i, j, S);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       kinds[f] = S.kind[f];
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(256) void kc_resid64(Resid64Args<TO> a) {
     const int ce = c < 0 ? 0 : c;
     double x[NL], bv[NL], hv[6];
     double zlo, zhi;
-    const CubeMeta& m = a.g.meta[ce];
+    MetaRO& m = meta_ro(a.g.meta, ce);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       x[k] = np[k];
@@ -999,7 +999,7 @@ __global__ __launch_bounds__(256) void kc_ir(IrArgs<T> a) {
 #pragma unroll
       for (int k = 0; k < NL; ++k) tile[C::tix(L.s, L.i, L.j, k)] = p[k];
       __syncthreads();
-      if (c >= 0) export_avg<NL, double>(a.pf_out, c, tile, a.g.meta[c], L);
+      if (c >= 0) export_avg<NL, double>(a.pf_out, c, tile, meta_ro(a.g.meta, c), L);
       __syncthreads();
     }
   }
@@ -1028,7 +1028,7 @@ __global__ __launch_bounds__(256) void k16_force(ForceArgs<TF> a) {
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
   const int n = a.g.n_cubes;
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
-    const int c = a.g.launch[w];
+    const int c = ro_load(a.g.launch, w);
     TF* base = a.uf + (size_t)c * Col<16>::F;
     if (a.body) {
       // alpha and the face sources of u~ are loaded together, before the decision; all three
@@ -1103,8 +1103,8 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
   const int n = a.g.n_cubes;
   const int t1 = t & 15, t2 = t >> 4;
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
-    const int c = a.g.launch[w];
-    const CubeMeta& m = a.g.meta[c];
+    const int c = ro_load(a.g.launch, w);
+    MetaRO& m = meta_ro(a.g.meta, c);
     const double ih = 1.0 / m.h;
     const bool forced = !a.body || a.body[c];  // u* stored, else u* = u~
     const TF* src[3] = {forced ? a.ustar[0] : a.u[0], forced ? a.ustar[1] : a.u[1],
@@ -1177,8 +1177,8 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
   const int t = threadIdx.x, i = t & 15, j = t >> 4;
   const int n = a.g.n_cubes;
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
-    const int c = a.g.launch[w];
-    const CubeMeta& m = a.g.meta[c];
+    const int c = ro_load(a.g.launch, w);
+    MetaRO& m = meta_ro(a.g.meta, c);
     double p[16], hv[6], rf[6];
     Slots S;
     slots<16, ML>(m, c, i, j, S);

@@ -40,6 +40,20 @@ __device__ __forceinline__ void st_nt(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
+// Tables that no kernel writes (cube metadata, the launch order) are read through the constant
+// address space: with a wave-uniform index that is a scalar load, counted apart from the vector
+// memory operations.  A vector load of the same value would make every wait on it (a branch on
+// a face kind, a readfirstlane of a cube index) also wait for all loads and stores issued
+// before it, the prefetched columns and the previous cube's stores included.
+template <typename T>
+__device__ __forceinline__ T ro_load(const T* p, size_t i) {
+  return ((const __attribute__((address_space(4))) T*)(p))[i];
+}
+// A cube's metadata in place, by reference through the constant address space (the helpers
+// that read metadata take it as a template type, so LDS copies work as well).
+using MetaRO = const __attribute__((address_space(4))) CubeMeta;
+__device__ __forceinline__ MetaRO& meta_ro(const CubeMeta* p, size_t i) { return ((MetaRO*)p)[i]; }
+
 template <int NL>
 struct Lv {
   static constexpr int N = NL, N2 = NL * NL, N3 = NL * NL * NL;
@@ -75,8 +89,8 @@ __device__ __forceinline__ int halo_idx(int f, int t1, int t2) {
 
 // Raw neighbour value across face f of a cube at tangential cell (t1, t2).
 // get(cube, face_of_that_cube, t1, t2) reads one value of that cube's face slab.
-template <int NL, typename T, class Get>
-__device__ __forceinline__ T nb_raw(const CubeMeta& m, int f, int t1, int t2, Get get) {
+template <int NL, typename T, class Get, class MT>
+__device__ __forceinline__ T nb_raw(const MT& m, int f, int t1, int t2, Get get) {
   const int of = f ^ 1;
   const int kd = m.kind[f];
   if (kd == FK_SAME) return get(m.nbr[f][0], of, t1, t2);
@@ -172,8 +186,8 @@ __device__ __forceinline__ void cell_of(int e, int& s, int& i, int& j, int& k) {
 }
 
 // Own coefficient of the side (face f) of cell (i,j,k) under rule R.
-template <int NL, int R>
-__device__ __forceinline__ double side_own(const CubeMeta& m, int f, int i, int j, int k) {
+template <int NL, int R, class MT>
+__device__ __forceinline__ double side_own(const MT& m, int f, int i, int j, int k) {
   const int d = f >> 1;
   const int c = d == 0 ? i : d == 1 ? j : k;
   const bool on = (f & 1) ? (c == NL - 1) : (c == 0);
