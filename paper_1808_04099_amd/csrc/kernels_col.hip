@@ -92,7 +92,7 @@ __device__ __forceinline__ void slots(const MT& m, int self, int t1, int t2, Slo
   using C = Col<NL>;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
-    const int kd = m.kind[f], of = f ^ 1;
+    const int kd = kind_of(m, f), of = f ^ 1;
     S.kind[f] = kd;
     int fo = self * C::F + f * C::N2 + t2 * NL + t1;
     int co = self * C::FH + f * C::H2 + (t2 >> 1) * C::H + (t1 >> 1);
@@ -101,7 +101,7 @@ __device__ __forceinline__ void slots(const MT& m, int self, int t1, int t2, Slo
       fo = c * C::F + of * C::N2 + t2 * NL + t1;
       co = c * C::FH + of * C::H2 + (t2 >> 1) * C::H + (t1 >> 1);
     } else if (ML && kd == FK_COARSER) {
-      const int qd = m.quad[f], c = m.nbr[f][0];
+      const int qd = quad_of(m, f), c = m.nbr[f][0];
       const int a = (qd & 1) * C::H + (t1 >> 1), b = (qd >> 1) * C::H + (t2 >> 1);
       fo = c * C::F + of * C::N2 + b * NL + a;
       co = c * C::FH + of * C::H2 + (b >> 1) * C::H + (a >> 1);
@@ -137,13 +137,13 @@ __device__ __forceinline__ void stage(T* tile, const T (&hv)[6], const LaneC<NL>
 template <int NL, typename T, class MT>
 __device__ __forceinline__ void diag(const MT& m, int i, int j, T& d0, T& dm, T& dl) {
   T c = T(6);
-  if (i == 0) c += T(RuleTab<RULE_P>::own(m.kind[0])) - T(1);
-  if (i == NL - 1) c += T(RuleTab<RULE_P>::own(m.kind[1])) - T(1);
-  if (j == 0) c += T(RuleTab<RULE_P>::own(m.kind[2])) - T(1);
-  if (j == NL - 1) c += T(RuleTab<RULE_P>::own(m.kind[3])) - T(1);
+  if (i == 0) c += T(RuleTab<RULE_P>::own(kind_of(m, 0))) - T(1);
+  if (i == NL - 1) c += T(RuleTab<RULE_P>::own(kind_of(m, 1))) - T(1);
+  if (j == 0) c += T(RuleTab<RULE_P>::own(kind_of(m, 2))) - T(1);
+  if (j == NL - 1) c += T(RuleTab<RULE_P>::own(kind_of(m, 3))) - T(1);
   dm = c;
-  d0 = c + T(RuleTab<RULE_P>::own(m.kind[4])) - T(1);
-  dl = c + T(RuleTab<RULE_P>::own(m.kind[5])) - T(1);
+  d0 = c + T(RuleTab<RULE_P>::own(kind_of(m, 4))) - T(1);
+  dl = c + T(RuleTab<RULE_P>::own(kind_of(m, 5))) - T(1);
 }
 
 // Write the six face slabs of a cube from the lane's column.
@@ -179,7 +179,7 @@ __device__ __forceinline__ void export_avg(T* xf, int c, const T* tile, const MT
   T* base = xf + (size_t)c * C::F + 6 * C::N2;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
-    if (m.kind[f] != FK_COARSER) continue;
+    if (kind_of(m, f) != FK_COARSER) continue;
     const int lay = (f & 1) ? NL - 1 : 0, d = f >> 1;
     T v[4];
 #pragma unroll
@@ -404,7 +404,7 @@ __device__ __forceinline__ void tri_column(const T* ct, const LaneC<NL>& L, T (&
 //            on every lane.
 // ------------------------------------------------------------------------------------------
 template <typename T, int NL, bool POST, bool ML, bool TRI = false>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 1) void kc_smooth(SmoothArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
   // sweep form (same update order): shifted columns before restriction; with the trilinear
@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
     const int c = ro_load(a.g.launch, w);
     MetaRO& m = meta_ro(a.g.meta, c);
     const double ih = 1.0 / m.h;
-    const bool forced = !a.body || a.body[c];  // u* stored, else u* = u~
+    const bool forced = !a.body || ro_byte(a.body, c) != 0;  // u* stored, else u* = u~
     const TF* src[3] = {forced ? a.ustar[0] : a.u[0], forced ? a.ustar[1] : a.u[1],
                         forced ? a.ustar[2] : a.u[2]};
     double acc[16];
@@ -1118,7 +1118,7 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
       for (int k = 0; k < 16; ++k) v[k] = ld_nt(src[2] + (size_t)c * 4096 + k * 256 + t);
       double lo, hi;  // face velocities on the -z and +z faces of the column
       {
-        const int k4 = m.kind[4], k5 = m.kind[5];
+        const int k4 = kind_of(m, 4), k5 = kind_of(m, 5);
         const double r4 = k4 <= FK_FINER ? RuleTab<RULE_U>::nbeff(k4) * double(nb_raw<16, TF>(m, 4, t1, t2, gf)) : 0.0;
         const double r5 = k5 <= FK_FINER ? RuleTab<RULE_U>::nbeff(k5) * double(nb_raw<16, TF>(m, 5, t1, t2, gf)) : 0.0;
         lo = 0.5 * (k4 == FK_INFLOW ? 2.0 * a.U_in : r4) + RuleTab<RULE_U>::own(k4) * double(v[0]);
@@ -1143,7 +1143,7 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int f = 2 * d + s;
-        const int kd = m.kind[f];
+        const int kd = kind_of(m, f);
         TF hv = TF(0);
         if (kd <= FK_FINER) hv = TF(RuleTab<RULE_U>::nbeff(kd)) * nb_raw<16, TF>(m, f, t1, t2, gf);
         else if (kd == FK_INFLOW) hv = TF(2.0 * (s ? -a.U_in : a.U_in));
@@ -1151,8 +1151,8 @@ __global__ __launch_bounds__(256) void k16_div(DivArgs<TF> a) {
       }
       __syncthreads();
       const int st = d == 0 ? 1 : 18;
-      const double own_m = (d == 0 ? i == 0 : j == 0) ? RuleTab<RULE_U>::own(m.kind[2 * d]) : 0.5;
-      const double own_p = (d == 0 ? i == 15 : j == 15) ? RuleTab<RULE_U>::own(m.kind[2 * d + 1]) : 0.5;
+      const double own_m = (d == 0 ? i == 0 : j == 0) ? RuleTab<RULE_U>::own(kind_of(m, 2 * d)) : 0.5;
+      const double own_p = (d == 0 ? i == 15 : j == 15) ? RuleTab<RULE_U>::own(kind_of(m, 2 * d + 1)) : 0.5;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int cc = tix16(i, j, k);
@@ -1189,21 +1189,23 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
 #pragma unroll
     for (int f = 0; f < 6; ++f) hv[f] = halo_val<double>(S.kind[f], rf[f]);
     const double ch = a.c * 0.5 / m.h;
-    const double ox_m = i == 0 ? RuleTab<RULE_P>::own(m.kind[0]) : 1.0;
-    const double ox_p = i == 15 ? RuleTab<RULE_P>::own(m.kind[1]) : 1.0;
-    const double oy_m = j == 0 ? RuleTab<RULE_P>::own(m.kind[2]) : 1.0;
-    const double oy_p = j == 15 ? RuleTab<RULE_P>::own(m.kind[3]) : 1.0;
-    const double oz_m = RuleTab<RULE_P>::own(m.kind[4]), oz_p = RuleTab<RULE_P>::own(m.kind[5]);
+    const double ox_m = i == 0 ? RuleTab<RULE_P>::own(kind_of(m, 0)) : 1.0;
+    const double ox_p = i == 15 ? RuleTab<RULE_P>::own(kind_of(m, 1)) : 1.0;
+    const double oy_m = j == 0 ? RuleTab<RULE_P>::own(kind_of(m, 2)) : 1.0;
+    const double oy_p = j == 15 ? RuleTab<RULE_P>::own(kind_of(m, 3)) : 1.0;
+    const double oz_m = RuleTab<RULE_P>::own(kind_of(m, 4)), oz_p = RuleTab<RULE_P>::own(kind_of(m, 5));
     const int cc = (j + 1) * 18 + (i + 1);
     // u* of plane k + 1 is loaded while plane k is computed (the loads would otherwise start
     // only after each plane's barrier)
     const size_t g0 = (size_t)c * 4096 + t;
-    const bool forced = !a.body || a.body[c];  // u* stored, else u* = u~
+    const bool forced = !a.body || ro_byte(a.body, c) != 0;  // u* stored, else u* = u~
     const TF* src[3] = {forced ? a.ustar[0] : a.u[0], forced ? a.ustar[1] : a.u[1],
                         forced ? a.ustar[2] : a.u[2]};
     TF us[3], usn[3];
+    // (loaded whether or not the component is written: a load under a branch makes the
+    // following waits conservative)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) usn[d] = a.unew[d] ? ld_nt(src[d] + g0) : TF(0);
+    for (int d = 0; d < 3; ++d) usn[d] = ld_nt(src[d] + g0);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       double* b = pl[k & 1];
@@ -1218,7 +1220,7 @@ __global__ __launch_bounds__(256) void k16_correct(CorrectArgs<TF> a) {
       for (int d = 0; d < 3; ++d) us[d] = usn[d];
       if (k < 15) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) usn[d] = a.unew[d] ? ld_nt(src[d] + g0 + (k + 1) * 256) : TF(0);
+        for (int d = 0; d < 3; ++d) usn[d] = ld_nt(src[d] + g0 + (k + 1) * 256);
       }
       __syncthreads();
       const size_t g = g0 + k * 256;

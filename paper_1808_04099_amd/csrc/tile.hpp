@@ -49,10 +49,26 @@ template <typename T>
 __device__ __forceinline__ T ro_load(const T* p, size_t i) {
   return ((const __attribute__((address_space(4))) T*)(p))[i];
 }
+// Byte i of a read-only byte table, from the dword that holds it (the table is padded to a
+// multiple of 4 bytes).
+__device__ __forceinline__ int ro_byte(const uint8_t* p, size_t i) {
+  const uint32_t w = ((const __attribute__((address_space(4))) uint32_t*)(p))[i >> 2];
+  return int((w >> (8 * (i & 3))) & 0xFFu);
+}
 // A cube's metadata in place, by reference through the constant address space (the helpers
 // that read metadata take it as a template type, so LDS copies work as well).
 using MetaRO = const __attribute__((address_space(4))) CubeMeta;
 __device__ __forceinline__ MetaRO& meta_ro(const CubeMeta* p, size_t i) { return ((MetaRO*)p)[i]; }
+// Face kind and quadrant of face f.  Through MetaRO each is taken from the dword that holds it
+// (scalar loads fetch whole dwords; a byte access would be a vector load again).
+__device__ __forceinline__ int meta_byte(MetaRO& m, int b) {
+  const uint32_t w = ((const __attribute__((address_space(4))) uint32_t*)&m)[b >> 2];
+  return int(int8_t(w >> (8 * (b & 3))));
+}
+__device__ __forceinline__ int kind_of(const CubeMeta& m, int f) { return m.kind[f]; }
+__device__ __forceinline__ int kind_of(MetaRO& m, int f) { return meta_byte(m, offsetof(CubeMeta, kind) + f); }
+__device__ __forceinline__ int quad_of(const CubeMeta& m, int f) { return m.quad[f]; }
+__device__ __forceinline__ int quad_of(MetaRO& m, int f) { return meta_byte(m, offsetof(CubeMeta, quad) + f); }
 
 template <int NL>
 struct Lv {
@@ -92,10 +108,10 @@ __device__ __forceinline__ int halo_idx(int f, int t1, int t2) {
 template <int NL, typename T, class Get, class MT>
 __device__ __forceinline__ T nb_raw(const MT& m, int f, int t1, int t2, Get get) {
   const int of = f ^ 1;
-  const int kd = m.kind[f];
+  const int kd = kind_of(m, f);
   if (kd == FK_SAME) return get(m.nbr[f][0], of, t1, t2);
   if (kd == FK_COARSER) {
-    const int q = m.quad[f];
+    const int q = quad_of(m, f);
     return get(m.nbr[f][0], of, (q & 1) * (NL / 2) + (t1 >> 1), (q >> 1) * (NL / 2) + (t2 >> 1));
   }
   if (kd == FK_FINER) {
@@ -191,7 +207,7 @@ __device__ __forceinline__ double side_own(const MT& m, int f, int i, int j, int
   const int d = f >> 1;
   const int c = d == 0 ? i : d == 1 ? j : k;
   const bool on = (f & 1) ? (c == NL - 1) : (c == 0);
-  return on ? RuleTab<R>::own(m.kind[f]) : RuleTab<R>::int_own;
+  return on ? RuleTab<R>::own(kind_of(m, f)) : RuleTab<R>::int_own;
 }
 
 // Fill the six halo slabs of every cube of the workgroup under rule R.
