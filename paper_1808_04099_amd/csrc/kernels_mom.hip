@@ -160,22 +160,65 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
     const int rp = rside ? NL + 1 : 0;
     const int ria = rd == 0 ? (i + 1) * M::W2 + rp : rp * M::W2 + i + 1;
     const Affine ra = rd == 0 ? rr[0] : rr[1];  // a select: a dynamic index would put rr in scratch
+    // The outputs of plane k are stored at the top of plane k + 1, after that plane's loads
+    // are issued: the vector-memory counter is in order, so a load issued after a store could
+    // not be consumed before the store completes.
+    double po[3] = {0.0, 0.0, 0.0}, ph[3] = {0.0, 0.0, 0.0};
+    auto put = [&](int kp) __attribute__((always_inline)) {
+      if (!live) return;
+      const size_t gp = cb + (size_t)kp * M::N2;
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        const double o = po[comp];
+        a.out[comp][gp] = TF(o);
+        if (a.hout[comp]) a.hout[comp][gp] = TF(ph[comp]);
+        if (a.outf[comp]) {  // two-layer faces of the output, cell by cell
+          TF* fb = a.outf[comp] + (size_t)c * M::FS;
+#pragma unroll
+          for (int L = 0; L < 2; ++L) {
+            if (i == L) fb[M::fidx(0, L, j, kp)] = TF(o);
+            if (i == NL - 1 - L) fb[M::fidx(1, L, j, kp)] = TF(o);
+            if (j == L) fb[M::fidx(2, L, i, kp)] = TF(o);
+            if (j == NL - 1 - L) fb[M::fidx(3, L, i, kp)] = TF(o);
+            if (kp == L) fb[M::fidx(4, L, i, j)] = TF(o);
+            if (kp == NL - 1 - L) fb[M::fidx(5, L, i, j)] = TF(o);
+          }
+        }
+      }
+    };
 #pragma unroll 1
     for (int k = 0; k < NL; ++k) {
       const double axk = double(a.a[0][cb + k * M::N2]), ayk = double(a.a[1][cb + k * M::N2]);
+      double qk[3];  // right-hand side (or previous H) of plane k
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        qk[comp] = 0.0;
+        if (MODE == MOM_CN_ITER) qk[comp] = double(a.rhs[comp][cb + k * M::N2]);
+        if (MODE == MOM_EXPLICIT && a.hprev[comp]) qk[comp] = double(a.hprev[comp][cb + k * M::N2]);
+      }
+      TF rgv[7];
+      if (ring) {
+        const size_t ko = (size_t)k * NL;
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+          rgv[2 * comp] = a.vf[comp][ro[0] + ko];
+          rgv[2 * comp + 1] = a.vf[comp][ro[1] + ko];
+        }
+        rgv[6] = a.af[rd][ro[0] + ko];
+      }
+      if (k > 0) put(k - 1);
       // plane k into LDS: interior, then the rings
 #pragma unroll
       for (int comp = 0; comp < 3; ++comp) pv[s][comp][(j + 2) * M::W4 + i + 2] = wv[comp][2];
       pa[s][0][(j + 1) * M::W2 + i + 1] = axk;
       pa[s][1][(j + 1) * M::W2 + i + 1] = ayk;
       if (ring) {
-        const size_t ko = (size_t)k * NL;
 #pragma unroll
         for (int comp = 0; comp < 3; ++comp) {
-          pv[s][comp][ridx0] = rr[comp].scale * double(a.vf[comp][ro[0] + ko]) + rr[comp].shift;
-          pv[s][comp][ridx1] = rr[comp].scale * double(a.vf[comp][ro[1] + ko]) + rr[comp].shift;
+          pv[s][comp][ridx0] = rr[comp].scale * double(rgv[2 * comp]) + rr[comp].shift;
+          pv[s][comp][ridx1] = rr[comp].scale * double(rgv[2 * comp + 1]) + rr[comp].shift;
         }
-        pa[s][rd][ria] = ra.scale * double(a.af[rd][ro[0] + ko]) + ra.shift;
+        pa[s][rd][ria] = ra.scale * double(rgv[6]) + ra.shift;
       }
       __syncthreads();
       const double Ux[2] = {0.5 * (pa[s][0][(j + 1) * M::W2 + i] + axk),
@@ -218,8 +261,7 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
         const double v0 = wv[comp][2];
         double o;
         if (MODE == MOM_EXPLICIT) {
-          const double hp = a.hprev[comp] ? double(a.hprev[comp][g]) : 0.0;
-          o = v0 + a.dt * (a.c1 * H + a.c2 * hp);
+          o = v0 + a.dt * (a.c1 * H + a.c2 * qk[comp]);
         } else if (MODE == MOM_CN_START) {
           const double rhs = v0 + 0.5 * a.dt * H;
           if (live) a.rhs[comp][g] = TF(rhs);
@@ -227,26 +269,12 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
           o = v0 + a.dt * H;  // Euler predictor as the first iterate
         } else {
           const double diag = fmax(1.0 + 0.5 * a.dt * (6.0 * a.nu * ih2 + dg), 0.5);
-          const double r = double(a.rhs[comp][g]) + 0.5 * a.dt * H - v0;
+          const double r = qk[comp] + 0.5 * a.dt * H - v0;
           acc += r * r;
           o = v0 + r / diag;
         }
-        if (live) {
-          a.out[comp][g] = TF(o);
-          if (a.hout[comp]) a.hout[comp][g] = TF(H);
-          if (a.outf[comp]) {  // two-layer faces of the output, cell by cell
-            TF* fb = a.outf[comp] + (size_t)c * M::FS;
-#pragma unroll
-            for (int L = 0; L < 2; ++L) {
-              if (i == L) fb[M::fidx(0, L, j, k)] = TF(o);
-              if (i == NL - 1 - L) fb[M::fidx(1, L, j, k)] = TF(o);
-              if (j == L) fb[M::fidx(2, L, i, k)] = TF(o);
-              if (j == NL - 1 - L) fb[M::fidx(3, L, i, k)] = TF(o);
-              if (k == L) fb[M::fidx(4, L, i, j)] = TF(o);
-              if (k == NL - 1 - L) fb[M::fidx(5, L, i, j)] = TF(o);
-            }
-          }
-        }
+        po[comp] = o;
+        ph[comp] = H;
       }
       __syncthreads();  // the next plane overwrites the LDS planes
       // rotate the z windows; the plane entering at k + 3 is the cube's, or a ghost plane
@@ -267,6 +295,7 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
       za[1] = za[2];
       za[2] = k + 2 < NL ? na : azh;
     }
+    put(NL - 1);
   }
   if (a.part) {
     const double tsum = block_sum(acc, red);

@@ -49,10 +49,13 @@ template <typename T>
 __device__ __forceinline__ T ro_load(const T* p, size_t i) {
   return ((const __attribute__((address_space(4))) T*)(p))[i];
 }
+// A dword that may alias any other type (the byte fields below are read as whole dwords).
+typedef uint32_t __attribute__((may_alias)) u32_alias;
+
 // Byte i of a read-only byte table, from the dword that holds it (the table is padded to a
 // multiple of 4 bytes).
 __device__ __forceinline__ int ro_byte(const uint8_t* p, size_t i) {
-  const uint32_t w = ((const __attribute__((address_space(4))) uint32_t*)(p))[i >> 2];
+  const uint32_t w = ((const __attribute__((address_space(4))) u32_alias*)(p))[i >> 2];
   return int((w >> (8 * (i & 3))) & 0xFFu);
 }
 // A cube's metadata in place, by reference through the constant address space (the helpers
@@ -62,7 +65,7 @@ __device__ __forceinline__ MetaRO& meta_ro(const CubeMeta* p, size_t i) { return
 // Face kind and quadrant of face f.  Through MetaRO each is taken from the dword that holds it
 // (scalar loads fetch whole dwords; a byte access would be a vector load again).
 __device__ __forceinline__ int meta_byte(MetaRO& m, int b) {
-  const uint32_t w = ((const __attribute__((address_space(4))) uint32_t*)&m)[b >> 2];
+  const uint32_t w = ((const __attribute__((address_space(4))) u32_alias*)&m)[b >> 2];
   return int(int8_t(w >> (8 * (b & 3))));
 }
 __device__ __forceinline__ int kind_of(const CubeMeta& m, int f) { return m.kind[f]; }
