@@ -303,8 +303,8 @@ int bcm_momentum(bcm_plan* plan, const bcm_momentum_in* in, bcm_momentum_out* ou
  *   u_tilde / u_star  three device fields of the field type each (u_star written; must not
  *                     alias u_tilde)
  *   U_p, F_p          optional [n][3] device FP64 outputs (interpolated velocity, force), or NULL
- * Errors: BCM_ERR_INVALID_ARG (NULL or aliased fields, dt or rho not positive; or particles
- * outside the mesh or with a support leaving their level or the domain: those are skipped, the
+ * Errors: BCM_ERR_INVALID_ARG (NULL or aliased fields, dt or rho not positive, 2^26 or more
+ * particles (32 lanes each); or particles outside the mesh or with a support leaving their level or the domain: those are skipped, the
  * others' forcing is in u_star, and bcm_last_error gives the count), BCM_ERR_UNSUPPORTED (no
  * point-location tables: a level's cubes span more than 2^26 lattice positions).  The call
  * waits for the stream (it reads the skip count back). */

@@ -3,10 +3,12 @@
 // discrete delta function (Eq. (ddeltai)), take the constraint force F = (rho/dt)(U_s - U)
 // and spread it back with the same weights (Eq. (ddeltap)): u* = u~ + (dt/rho) f.
 //
-// One lane per particle.  The paper groups the particles into per-cube sets so that the cells
-// around a particle follow from index arithmetic in its cube; here the lane finds the particle's
-// cube itself (dense per-level lattice tables, finest level first) and walks from it to the
-// face neighbours, so the caller passes plain arrays.  The support is the 3 x 3 x 3 cells
+// Thirty-two lanes (half a wavefront) per particle, lane e < 27 for cell e of the support: the
+// gather is summed across the lanes and every lane spreads to its own cell.  The paper groups
+// the particles into per-cube sets so that the cells around a particle follow from index
+// arithmetic in its cube; here the lanes find the particle's cube themselves (dense per-level
+// lattice tables, finest level first) and walk from it to the face neighbours, so the caller
+// passes plain arrays.  The support is the 3 x 3 x 3 cells
 // around the cell holding the particle, all of its cube's level; a particle outside the mesh,
 // or whose support would leave that level's cubes or the domain, is skipped and counted.
 // Spreading adds with atomics: contributions of particles that share a cell are summed in
@@ -52,13 +54,14 @@ __device__ __forceinline__ int ib_locate(const IbArgs<TF>& a, const double (&X)[
 
 template <typename TF>
 __global__ __launch_bounds__(256) void k_ib_force(IbArgs<TF> a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = threadIdx.x & 31;                                 // cell of the support
+  const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 5;     // the same on 32 lanes
   if (p >= a.n_particles) return;
   const double X[3] = {a.X[3 * (size_t)p], a.X[3 * (size_t)p + 1], a.X[3 * (size_t)p + 2]};
   int pos[3], lev = 0;
   const int c0 = ib_locate(a, X, pos, lev);
   if (c0 < 0) {
-    atomicAdd(a.errors, 1u);
+    if (e == 0) atomicAdd(a.errors, 1u);
     return;
   }
   const int n = a.n;
@@ -78,11 +81,13 @@ __global__ __launch_bounds__(256) void k_ib_force(IbArgs<TF> a) {
   }
   // cell e of the 27 (e = ex + 3 ey + 9 ez): its cube, reached from the particle's cube by
   // steps to face neighbours of the same level along x, then y, then z, and its offset there;
-  // false when a step meets a face without a same-level neighbour
-  auto cell_at = [&](int e, size_t& g) {
+  // not found when a step meets a face without a same-level neighbour
+  size_t g = 0;
+  bool ok = true;
+  double we = 0.0;
+  if (e < 27) {
     const int dd[3] = {e % 3 - 1, (e / 3) % 3 - 1, e / 9 - 1};
     int c = c0, loc[3];
-    bool ok = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       loc[d] = cell[d] + dd[d];
@@ -95,19 +100,21 @@ __global__ __launch_bounds__(256) void k_ib_force(IbArgs<TF> a) {
       }
     }
     g = (size_t)c * n * n * n + (loc[2] * n + loc[1]) * n + loc[0];
-    return ok;
-  };
-  double U[3] = {0.0, 0.0, 0.0};
-  bool ok = true;
-  for (int e = 0; e < 27; ++e) {
-    size_t g;
-    ok = cell_at(e, g) && ok;
-    const double we = w[0][e % 3] * w[1][(e / 3) % 3] * w[2][e / 9];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) U[d] += we * double(a.u[d][g]);
+    we = w[0][e % 3] * w[1][(e / 3) % 3] * w[2][e / 9];
   }
-  if (!ok) {
-    atomicAdd(a.errors, 1u);
+  // gather: each lane's term, summed over the 32 lanes (every lane ends with the sums)
+  double U[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) U[d] = e < 27 ? we * double(a.u[d][g]) : 0.0;
+  int all = ok ? 1 : 0;
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) U[d] += __shfl_xor(U[d], o, 32);
+    all = min(all, __shfl_xor(all, o, 32));
+  }
+  if (!all) {
+    if (e == 0) atomicAdd(a.errors, 1u);
     return;
   }
   double F[3];
@@ -115,17 +122,14 @@ __global__ __launch_bounds__(256) void k_ib_force(IbArgs<TF> a) {
   for (int d = 0; d < 3; ++d) {
     const double us = a.Us ? a.Us[3 * (size_t)p + d] : a.usc[d];
     F[d] = a.rho_dt * (us - U[d]);
-    if (a.Up) a.Up[3 * (size_t)p + d] = U[d];
-    if (a.Fp) a.Fp[3 * (size_t)p + d] = F[d];
+    if (e == 0 && a.Up) a.Up[3 * (size_t)p + d] = U[d];
+    if (e == 0 && a.Fp) a.Fp[3 * (size_t)p + d] = F[d];
   }
   const double dV = a.dV ? a.dV[p] : h * h * h;
   const double scale = a.dt_rho * dV / (h * h * h);
-  for (int e = 0; e < 27; ++e) {
-    size_t g;
-    (void)cell_at(e, g);
-    const double we = w[0][e % 3] * w[1][(e / 3) % 3] * w[2][e / 9] * scale;
+  if (e < 27) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) atomicAdd(a.ustar[d] + g, TF(we * F[d]));
+    for (int d = 0; d < 3; ++d) atomicAdd(a.ustar[d] + g, TF(we * scale * F[d]));
   }
 }
 
@@ -136,7 +140,9 @@ __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 template <typename TF>
 hipError_t launch_ib_force(const IbArgs<TF>& a, hipStream_t s) {
   if (a.n_particles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ib_force<TF>), dim3((a.n_particles + 255) / 256), dim3(256), 0, s, a);
+  const long long lanes = 32ll * a.n_particles;
+  if (lanes > 0x7FFFFFFFll) return hipErrorInvalidValue;  // lane indices are 32-bit
+  hipLaunchKernelGGL((k_ib_force<TF>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

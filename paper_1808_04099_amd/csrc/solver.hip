@@ -1513,8 +1513,10 @@ int bcm_ib_force(bcm_plan* P, const bcm_particles* pt, const void* const u_tilde
                  double dt, double rho, double* U_p, double* F_p, void* stream) {
   int st = check_bound(P);
   if (st) return st;
-  if (!pt || !u_tilde || !u_star || pt->n < 0 || (pt->n > 0 && !pt->X) || !(dt > 0) || !(rho > 0)) {
-    set_error("bcm_ib_force: NULL argument, negative particle count, or dt / rho not positive");
+  if (!pt || !u_tilde || !u_star || pt->n < 0 || pt->n >= (1 << 26) || (pt->n > 0 && !pt->X) ||
+      !(dt > 0) || !(rho > 0)) {
+    set_error("bcm_ib_force: NULL argument, particle count negative or not below 2^26, or dt / rho "
+              "not positive");
     return BCM_ERR_INVALID_ARG;
   }
   for (int d = 0; d < 3; ++d)
