@@ -9,8 +9,8 @@
 //   data: per cube the G = n^3/32 group widths (bytes, zero-padded to 4), then for each group
 //   its w 32-bit words, code j at bits j w .. j w + w - 1.
 //
-// One workgroup per cube (grid-stride), the cube in LDS (FP64, 32 KB at n = 16); lifting runs
-// one line per lane.  The lifting scales by 1/2 and 1/4 (exact), the quantiser divides by the
+// One workgroup per cube (grid-stride), the cube in LDS (FP64, 34 KB at n = 16 with its rows
+// padded); lifting runs one line per lane.  The lifting scales by 1/2 and 1/4 (exact), the quantiser divides by the
 // step (IEEE division) and rounds half to even, so the codes and bytes depend on no operation
 // order that another implementation of the same steps could do differently.
 #include "kernels.hpp"
@@ -67,21 +67,30 @@ __device__ __forceinline__ void lift_inv(double* c, int base, int st) {
   }
 }
 
+// The cube in LDS with each x row padded by one value (row pitch NL + 1): lanes lifting x lines
+// read values NL + 1 apart, not NL (a multiple of the bank count, every lane on one bank).
+template <int NL>
+struct Pad {
+  static constexpr int R = NL + 1, P = NL * R, SIZE = NL * P;
+  __device__ static int of(int e) { return e + e / NL; }  // element e = (k NL + j) NL + i
+};
+
 // One axis of one level over the M^3 corner block: lane t < M^2 takes one line.
 template <int NL, int M, bool INV>
 __device__ __forceinline__ void lift_axis(double* c, int axis) {
+  using PD = Pad<NL>;
   for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
     const int a = t % M, b = t / M;
     int base, st;
     if (axis == 0) {  // lines along i at (j, k) = (a, b)
-      base = (b * NL + a) * NL;
+      base = b * PD::P + a * PD::R;
       st = 1;
     } else if (axis == 1) {  // along j at (i, k)
-      base = b * NL * NL + a;
-      st = NL;
+      base = b * PD::P + a;
+      st = PD::R;
     } else {  // along k at (i, j)
-      base = b * NL + a;
-      st = NL * NL;
+      base = b * PD::R + a;
+      st = PD::P;
     }
     if (INV)
       lift_inv<M>(c, base, st);
@@ -115,18 +124,35 @@ __device__ __forceinline__ int bit_length(uint32_t v) { return v ? 32 - __clz(v)
 template <int NL>
 __global__ __launch_bounds__(256) void k_wc_encode(CodecArgs a) {
   constexpr int N3 = NL * NL * NL, G = N3 / 32;
-  __shared__ double c[N3];
+  __shared__ double c[Pad<NL>::SIZE];
   __shared__ int wsum[8];
+  // the next cube's values are loaded before this cube's codes are stored (a load issued after
+  // a store would wait for it in the in-order memory counter)
+  constexpr int PER = (N3 + 255) / 256;
+  double nx[PER];
+  auto fetch = [&](int cb) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = r * 256 + threadIdx.x;
+      nx[r] = e < N3 ? a.field[(size_t)cb * N3 + e] : 0.0;
+    }
+  };
+  if (blockIdx.x < a.n_cubes) fetch(blockIdx.x);
   for (int cube = blockIdx.x; cube < a.n_cubes; cube += gridDim.x) {
-    for (int e = threadIdx.x; e < N3; e += 256) c[e] = a.field[(size_t)cube * N3 + e];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = r * 256 + threadIdx.x;
+      if (e < N3) c[Pad<NL>::of(e)] = nx[r];
+    }
     __syncthreads();
+    if (cube + gridDim.x < a.n_cubes) fetch(cube + gridDim.x);
     dwt_fwd<NL, NL>(c);
     int wacc = 0;
     for (int e0 = 0; e0 < N3; e0 += 256) {
       const int e = e0 + threadIdx.x;  // the 32 lanes of each half-wave form one group
       uint32_t z = 0;
       if (e < N3) {
-        const double q = rint(c[e] / a.step);
+        const double q = rint(c[Pad<NL>::of(e)] / a.step);
         if (!(fabs(q) < 1073741824.0)) {  // 2^30; also catches NaN
           atomicOr(a.flags, 1u);
         } else {
@@ -247,7 +273,7 @@ __global__ __launch_bounds__(256) void k_wc_pack(CodecArgs a) {
 template <int NL>
 __global__ __launch_bounds__(256) void k_wc_decode(CodecArgs a) {
   constexpr int N3 = NL * NL * NL, G = N3 / 32, GP = (G + 3) / 4 * 4;
-  __shared__ double c[N3];
+  __shared__ double c[Pad<NL>::SIZE];
   __shared__ int wpre[G + 1];
   __shared__ uint8_t wid[G];
   const unsigned char* h = static_cast<const unsigned char*>(a.stream_in);
@@ -286,11 +312,11 @@ __global__ __launch_bounds__(256) void k_wc_decode(CodecArgs a) {
         z = (two >> sh) & ((w == 32) ? 0xFFFFFFFFull : ((1ull << w) - 1));
       }
       const long long q = (z & 1) ? -(long long)((z + 1) >> 1) : (long long)(z >> 1);
-      c[e] = double(q) * a.step;
+      c[Pad<NL>::of(e)] = double(q) * a.step;
     }
     __syncthreads();
     dwt_inv<NL, NL>(c);
-    for (int e = threadIdx.x; e < N3; e += 256) a.field_out[(size_t)cube * N3 + e] = c[e];
+    for (int e = threadIdx.x; e < N3; e += 256) a.field_out[(size_t)cube * N3 + e] = c[Pad<NL>::of(e)];
     __syncthreads();
   }
 }
