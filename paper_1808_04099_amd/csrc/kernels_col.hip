@@ -17,7 +17,10 @@
 // load issued before it (the prefetched columns included).
 //
 // Whole-field values are read and written with non-temporal hints (each is touched once per
-// launch); face slabs, metadata and scalars use ordinary cached accesses.
+// launch); face slabs and scalars use ordinary cached accesses.  The cube metadata and the
+// launch table are read with scalar loads (ro_load, meta_ro): the vector-memory counter is in
+// order, so a wait on a vector load of a face kind or a cube index would also wait for the
+// prefetched columns and the previous cube's stores.
 //
 // Multi-level meshes (2:1 faces) use the ML variants: one halo value per face cell still, the
 // finer side exporting 2x2 means of the faces that border a coarser cube (face_stride).
