@@ -110,6 +110,36 @@ def test_cell_only_correction_matches_face_output_path(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed_f32fields"])
+def test_body_cube_forcing_matches_full_forcing(precision):
+    """16^3 cubes with the body in a few cubes only: the forcing kernel then stores u* only in
+    those cubes and passes u~ on elsewhere (u* = u~ where alpha = 0).  With the face-velocity
+    output every cube is forced and stored; the right-hand side and the pressure must be
+    bit-identical, the cell velocities equal to the correction kernels' rounding."""
+    m = uniform_mesh((4, 2, 2), 0.25, 16, CHANNEL_BC)
+    rng = np.random.default_rng(9)
+    u = uniform_random_velocity(m, 10, 0.3, (1.0, 0.0, 0.0))
+    alpha = np.zeros((m.n_cubes, m.n ** 3))
+    alpha[[3, 6]] = rng.uniform(0.0, 1.0, (2, m.n ** 3))   # two body cubes of 16
+    alpha[9, :100] = 1.0                                   # one partly covered cube
+    alpha = alpha.ravel()
+    f32 = precision == "mixed_f32fields"
+    if f32:
+        u = u.astype(np.float32).astype(np.float64)
+    plan = plan_for(m, precision)
+    ft = plan.field_dtype
+    args = ([dev(u[d], ft) for d in range(3)], dev(alpha, ft), 0.8, 0.004, 1.0)
+    full = plan.project(*args, face_u=True, want_b=True)
+    sel = plan.project(*args, face_u=False, want_b=True)
+    assert np.array_equal(host(full["b"]), host(sel["b"]))
+    assert np.array_equal(host(full["p"]), host(sel["p"]))
+    uf = np.stack([host(x) for x in full["u_new"]])
+    us = np.stack([host(x) for x in sel["u_new"]])
+    assert rel_err(us, uf) <= (1e-6 if f32 else 1e-13)
+    ref = OP.project(FVMesh(m), u, alpha, (0, 0, 0), 0.8, 0.004, 1.0)
+    assert rel_err(us, ref["u_new"]) <= (1e-5 if f32 else 1e-7)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_f32fields"])
 def test_recompute_matches_projection(precision):
     m, u, alpha = _case("multilevel_small_n4")
     plan = plan_for(m, precision)
