@@ -25,6 +25,7 @@
 // Multi-level meshes (2:1 faces) use the ML variants: one halo value per face cell still, the
 // finer side exporting 2x2 means of the faces that border a coarser cube (face_stride).
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "tile.hpp"
@@ -201,6 +202,15 @@ __device__ __forceinline__ T nbsum(const T* tile, const T (&x)[NL], int k, int c
   const T zm = k > 0 ? x[k > 0 ? k - 1 : 0] : zlo;
   const T zp = k < NL - 1 ? x[k < NL - 1 ? k + 1 : NL - 1] : zhi;
   return tile[c - 1] + tile[c + 1] + tile[c - W] + tile[c + W] + zm + zp;
+}
+
+// The same sum in the halo-free tile of the 16^3 pre-smoother: neighbours at zb[] + plane
+// offset o, zero z halo.
+template <int NL, typename T>
+__device__ __forceinline__ T nbsum_z(const T* tile, const int (&zb)[4], int o, const T (&x)[NL], int k) {
+  const T zm = k > 0 ? x[k > 0 ? k - 1 : 0] : T(0);
+  const T zp = k < NL - 1 ? x[k < NL - 1 ? k + 1 : NL - 1] : T(0);
+  return tile[zb[0] + o] + tile[zb[1] + o] + tile[zb[2] + o] + tile[zb[3] + o] + zm + zp;
 }
 
 // Zero the partial sums past the grid, up to the count the reduction reads.
@@ -405,6 +415,13 @@ __device__ __forceinline__ void tri_column(const T* ct, const LaneC<NL>& L, T (&
 //   shifted: the column is copied into slots shifted by the parity (slot s = k + par + 1, the
 //            z halo in slots par and NL + par + 1), so that one colour sits in the same slots
 //            on every lane.
+// In the shifted form a lane of parity 1 works one plane below its neighbours of parity 0.
+// With the (NL+2)-wide rows that puts lanes of a wavefront on the same LDS bank.  The 16^3
+// pre-smoother of single-level meshes therefore keeps a tile without halo (ZL): rows of NL
+// cells, planes of NL^2 cells followed by 64 zeros, a plane pitch that is a multiple of 64
+// words.  A lane on a cube face reads one of the zeros instead of its halo cell (the halo of a
+// pre-smoother is zero), picked so that its bank is one the other lanes of the wavefront leave
+// free.  Every access of the sweeps then hits 64 distinct banks (32 per half-wavefront).
 // ------------------------------------------------------------------------------------------
 template <typename T, int NL, bool POST, bool ML, bool TRI = false>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothArgs<T> a) {
@@ -413,10 +430,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
   // sweep form (same update order): shifted columns before restriction; with the trilinear
   // prolongation the paired form in FP32 (fewer registers), else the masked form
   constexpr int SWEEP = !POST ? 2 : (TRI && sizeof(T) == 4 ? 1 : 0);
+  // the halo-free tile of the 16^3 pre-smoother (plane pitch ZP words)
+  constexpr bool ZL = !POST && NL == 16 && !ML;
+  constexpr int ZP = C::N2 + 64, TSL = ZL ? NL * ZP : C::TS;
   // pre-smoother below the finest level: the finer level's face correction is applied here
   constexpr bool RFX = !POST && NL < 16;
   constexpr int NF = RFX ? 2 * NL : NL;  // the finer level
-  __shared__ T tile[C::CPB * C::TS];
+  __shared__ T tile[C::CPB * TSL];
   __shared__ T hsum[RFX ? C::CPB * 6 * C::N2 : 1];  // per cube and face: 2x2 sums of halo values
   __shared__ T ctile[TRI ? C::CPB * Pro<NL>::P3 : 1];
   __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
@@ -428,6 +448,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
   const int i = L.i, j = L.j;
   const int U = col_units(C::CPB, a.g.n_cubes), G = gridDim.x;
   const bool dots = POST && a.part_zr != nullptr;
+  // ZL: the lane's cell in plane 0 and its x-, x+, y-, y+ neighbours there (a zero of the
+  // plane's zero block on a cube face: bank 16 (j mod 4) + 15, 16 (j mod 4), 48 + i and i)
+  const int zc = j * NL + i;
+  const int zb[4] = {i > 0 ? zc - 1 : C::N2 + 16 * (j & 3) + 15, i < NL - 1 ? zc + 1 : C::N2 + 16 * (j & 3),
+                     j > 0 ? zc - NL : C::N2 + 48 + i, j < NL - 1 ? zc + NL : C::N2 + i};
+  if (ZL) {
+    for (int e = t; e < NL * 64; e += 256) tile[(e >> 6) * ZP + C::N2 + (e & 63)] = T(0);
+  }
   T nx[NL], nb[NL], nxc[C::H], rf[6], rc[6];
   int kinds[6];
   // face correction: raw finer-level halo values of the four finer cells (t1, t2) =
@@ -519,14 +547,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
     for (int k = 0; k < NL; ++k) {
       if (!TRI) x[k] = POST ? nx[k] + nxc[k >> 1] : T(0);
       bv[k] = nb[k];
-      tile[C::tix(L.s, i, j, k)] = x[k];
+      // (a pre-smoother's first pass writes its colour before anything reads the tile, and
+      // the other colour is read only after its own first pass)
+      if (POST || a.sweeps == 0) tile[ZL ? k * ZP + zc : C::tix(L.s, i, j, k)] = x[k];
     }
     if (POST) {
       T hv[6];
 #pragma unroll
       for (int f = 0; f < 6; ++f) hv[f] = halo_val<T>(kinds[f], rf[f] + (TRI ? eh[f] : rc[f]));
       stage<NL, T>(tile, hv, L, zlo, zhi);
-    } else {
+    } else if (!ZL) {
 #pragma unroll
       for (int f = 0; f < 4; ++f) tile[C::halo(L.s, f, i, j)] = T(0);
     }
@@ -549,7 +579,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
     const double vol = m.vol;
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
-    __syncthreads();
+    if (POST || RFX || a.sweeps == 0) __syncthreads();
     if constexpr (RFX) {
       // the finer level's restriction lacked the cross-cube terms of its residual: for each
       // face the cell lies on (x, y, then z), -(1/8) of the sum of its 2x2 finer halo values
@@ -634,33 +664,55 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
       y[sl] = par ? col_at(sl - 2) : col_at(sl - 1);
       yb[sl] = par ? b_at(sl - 2) : b_at(sl - 1);
     }
-    const int tb = C::tix(L.s, i, j, 0) - (1 + par) * C::P;  // LDS index of slot s: tb + s P
-    for (int sw = 0; sw < a.sweeps; ++sw) {
+    // LDS index of slot s: tb + s P (ZL: tz[0] + s ZP, the neighbours tz[1..4] + s ZP)
+    const int tb = C::tix(L.s, i, j, 0) - (1 + par) * C::P;
+    const int zs = (1 + par) * ZP;
+    const int tz[5] = {zc - zs, zb[0] - zs, zb[1] - zs, zb[2] - zs, zb[3] - zs};
+    // one colour pass (red-black order from the zero initial guess); RD = false in the
+    // first pass, whose neighbours (the other colour and the halo) are still zero and are not
+    // read: its sum is +0, as the sum of the zeros would be
+    auto pass = [&](auto colour_c, auto rd_c) {
+      constexpr int colour = decltype(colour_c)::value;
+      constexpr bool RD = decltype(rd_c)::value;
   #pragma unroll
-      for (int col = 0; col < 2; ++col) {
-        const int colour = POST ? (col ^ 1) : col;
-  #pragma unroll
-        for (int sl = 1; sl <= NL + 1; ++sl) {
-          if ((sl & 1) != (colour ^ 1)) continue;  // the colour's slots (the same on every lane)
-          // slot 1 is a cell only on par = 0 lanes, slot NL + 1 only on par = 1 lanes
-          const bool valid = sl == 1 ? par == 0 : (sl == NL + 1 ? par == 1 : true);
-          const int cc = tb + sl * C::P;
-          const T sum = tile[valid ? cc - 1 : 0] + tile[valid ? cc + 1 : 0] +
-                        tile[valid ? cc - C::W : 0] + tile[valid ? cc + C::W : 0] + y[sl - 1] + y[sl + 1];
-          // k = sl - 1 - par: the first cell sits at slot 1 or 2, the last at NL or NL + 1
-          const T id = sl == 1 ? i0 : (sl == 2 ? (par ? i0 : im)
-                                               : (sl == NL ? (par ? im : il) : (sl == NL + 1 ? il : im)));
-          const T xn = (sum - h2 * yb[sl]) * id;
-          if (sl == 1 || sl == NL + 1) {
-            y[sl] = valid ? xn : y[sl];
-            if (valid) tile[cc] = xn;
-          } else {
-            y[sl] = xn;
-            tile[cc] = xn;
-          }
+      for (int sl = 1; sl <= NL + 1; ++sl) {
+        if ((sl & 1) != (colour ^ 1)) continue;  // the colour's slots (the same on every lane)
+        // slot 1 is a cell only on par = 0 lanes, slot NL + 1 only on par = 1 lanes
+        const bool valid = sl == 1 ? par == 0 : (sl == NL + 1 ? par == 1 : true);
+        const int cc = ZL ? tz[0] + sl * ZP : tb + sl * C::P;
+        T sum = T(0);
+        if constexpr (RD && ZL) {
+          // a lane without a cell here reads the plane next to it (same banks), unused
+          const int o = sl * ZP + (valid ? 0 : (sl == 1 ? ZP : -ZP));
+          sum = tile[tz[1] + o] + tile[tz[2] + o] + tile[tz[3] + o] + tile[tz[4] + o] + y[sl - 1] + y[sl + 1];
+        } else if constexpr (RD) {
+          sum = tile[valid ? cc - 1 : 0] + tile[valid ? cc + 1 : 0] +
+                tile[valid ? cc - C::W : 0] + tile[valid ? cc + C::W : 0] + y[sl - 1] + y[sl + 1];
         }
-        __syncthreads();
+        // k = sl - 1 - par: the first cell sits at slot 1 or 2, the last at NL or NL + 1
+        const T id = sl == 1 ? i0 : (sl == 2 ? (par ? i0 : im)
+                                             : (sl == NL ? (par ? im : il) : (sl == NL + 1 ? il : im)));
+        const T xn = (sum - h2 * yb[sl]) * id;
+        if (sl == 1 || sl == NL + 1) {
+          y[sl] = valid ? xn : y[sl];
+          if (valid) tile[cc] = xn;
+        } else {
+          y[sl] = xn;
+          tile[cc] = xn;
+        }
       }
+      __syncthreads();
+    };
+    static_assert(!POST, "the shifted form is the pre-smoother's");
+    using C0 = std::integral_constant<int, 0>;
+    using C1 = std::integral_constant<int, 1>;
+    if (a.sweeps > 0) {
+      pass(C0{}, std::false_type{});
+      pass(C1{}, std::true_type{});
+    }
+    for (int sw = 1; sw < a.sweeps; ++sw) {
+      pass(C0{}, std::true_type{});
+      pass(C1{}, std::true_type{});
     }
   #pragma unroll
     for (int k = 0; k < NL; ++k) x[k] = par ? y[k + 2] : y[k + 1];
@@ -689,7 +741,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
         for (int q2 = 0; q2 < 2; ++q2) {
           const int k = 2 * kk + q2;
           const T d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
-          const T sum = nbsum<NL, T>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
+          const T sum = ZL ? nbsum_z<NL, T>(tile, zb, k * ZP, x, k)
+                           : nbsum<NL, T>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
           acc += bv[k] - (sum - d * x[k]) * ih2;
         }
         rsum[(L.s * C::H + kk) * C::N2 + L.l] = acc;
