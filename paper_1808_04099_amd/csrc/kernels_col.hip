@@ -204,6 +204,15 @@ __device__ __forceinline__ T nbsum(const T* tile, const T (&x)[NL], int k, int c
   return tile[c - 1] + tile[c + 1] + tile[c - W] + tile[c + W] + zm + zp;
 }
 
+// The same sum in the halo-free tile of the 16^3 pre-smoother: neighbours at zb[] + plane
+// offset o, zero z halo.
+template <int NL, typename T>
+__device__ __forceinline__ T nbsum_z(const T* tile, const int (&zb)[4], int o, const T (&x)[NL], int k) {
+  const T zm = k > 0 ? x[k > 0 ? k - 1 : 0] : T(0);
+  const T zp = k < NL - 1 ? x[k < NL - 1 ? k + 1 : NL - 1] : T(0);
+  return tile[zb[0] + o] + tile[zb[1] + o] + tile[zb[2] + o] + tile[zb[3] + o] + zm + zp;
+}
+
 // Zero the partial sums past the grid, up to the count the reduction reads.
 __device__ __forceinline__ void zero_tail(double* part, int units) {
   for (int k = blockIdx.x + gridDim.x; k < fine_grid(units); k += gridDim.x) part[k] = 0.0;
@@ -662,18 +671,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
     // one colour pass (red-black order from the zero initial guess); RD = false in the
     // first pass, whose neighbours (the other colour and the halo) are still zero and are not
     // read: its sum is +0, as the sum of the zeros would be
-    // neighbour sum of slot sl (x-, x+, y-, y+, z-, z+)
-    auto nsum = [&](int sl, bool valid) -> T {
-      if constexpr (ZL) {
-        // a lane without a cell here reads the plane next to it (same banks), unused
-        const int o = sl * ZP + (valid ? 0 : (sl == 1 ? ZP : -ZP));
-        return tile[tz[1] + o] + tile[tz[2] + o] + tile[tz[3] + o] + tile[tz[4] + o] + y[sl - 1] + y[sl + 1];
-      } else {
-        const int cc = tb + sl * C::P;
-        return tile[valid ? cc - 1 : 0] + tile[valid ? cc + 1 : 0] +
-               tile[valid ? cc - C::W : 0] + tile[valid ? cc + C::W : 0] + y[sl - 1] + y[sl + 1];
-      }
-    };
     auto pass = [&](auto colour_c, auto rd_c) {
       constexpr int colour = decltype(colour_c)::value;
       constexpr bool RD = decltype(rd_c)::value;
@@ -684,7 +681,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
         const bool valid = sl == 1 ? par == 0 : (sl == NL + 1 ? par == 1 : true);
         const int cc = ZL ? tz[0] + sl * ZP : tb + sl * C::P;
         T sum = T(0);
-        if constexpr (RD) sum = nsum(sl, valid);
+        if constexpr (RD && ZL) {
+          // a lane without a cell here reads the plane next to it (same banks), unused
+          const int o = sl * ZP + (valid ? 0 : (sl == 1 ? ZP : -ZP));
+          sum = tile[tz[1] + o] + tile[tz[2] + o] + tile[tz[3] + o] + tile[tz[4] + o] + y[sl - 1] + y[sl + 1];
+        } else if constexpr (RD) {
+          sum = tile[valid ? cc - 1 : 0] + tile[valid ? cc + 1 : 0] +
+                tile[valid ? cc - C::W : 0] + tile[valid ? cc + C::W : 0] + y[sl - 1] + y[sl + 1];
+        }
         // k = sl - 1 - par: the first cell sits at slot 1 or 2, the last at NL or NL + 1
         const T id = sl == 1 ? i0 : (sl == 2 ? (par ? i0 : im)
                                              : (sl == NL ? (par ? im : il) : (sl == NL + 1 ? il : im)));
@@ -710,27 +714,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
       pass(C0{}, std::true_type{});
       pass(C1{}, std::true_type{});
     }
-    // residual for the restriction (with the zero halo of the sweeps), summed over each
-    // column pair (2 kk, 2 kk + 1) into rsum
-    if (a.bc && a.sweeps > 0) {
-      // a colour-1 cell's residual is zero after the last pass (its neighbours, all colour 0,
-      // have not changed since its update): each pair holds the residual of its one colour-0
-      // cell, at the odd slots
-      const T ih2 = T(1) / h2;
-  #pragma unroll
-      for (int sl = 1; sl <= NL + 1; sl += 2) {
-        const bool valid = sl == 1 ? par == 0 : (sl == NL + 1 ? par == 1 : true);
-        const T d = sl == 1 ? d0 : (sl == NL + 1 ? dl : dm);
-        const T r = yb[sl] - (nsum(sl, valid) - d * y[sl]) * ih2;
-        const int k = sl - 1 - par;
-        if (valid) rsum[(L.s * C::H + (k >> 1)) * C::N2 + L.l] = r;
-      }
-    } else if (a.bc) {
-      // no sweep: x = 0 and the residual is b
-  #pragma unroll
-      for (int kk = 0; kk < C::H; ++kk)
-        rsum[(L.s * C::H + kk) * C::N2 + L.l] = par ? yb[2 * kk + 2] + yb[2 * kk + 3] : yb[2 * kk + 1] + yb[2 * kk + 2];
-    }
   #pragma unroll
     for (int k = 0; k < NL; ++k) x[k] = par ? y[k + 2] : y[k + 1];
     }
@@ -750,7 +733,20 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
     if (!POST && a.bc) {
       // residual with the halo the sweeps used (zero across cube faces), summed over the 2x2x2
       // children of each coarse cell; the face correction adds the cross-cube terms
-      // (the shifted sweep form has stored the column-pair sums in rsum)
+      const T ih2 = T(1) / h2;
+#pragma unroll
+      for (int kk = 0; kk < C::H; ++kk) {
+        T acc = T(0);
+#pragma unroll
+        for (int q2 = 0; q2 < 2; ++q2) {
+          const int k = 2 * kk + q2;
+          const T d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
+          const T sum = ZL ? nbsum_z<NL, T>(tile, zb, k * ZP, x, k)
+                           : nbsum<NL, T>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
+          acc += bv[k] - (sum - d * x[k]) * ih2;
+        }
+        rsum[(L.s * C::H + kk) * C::N2 + L.l] = acc;
+      }
       __syncthreads();
       for (int e = t; e < C::CPB * C::H3; e += 256) {
         const int s2 = e / C::H3, le = e - s2 * C::H3;
