@@ -34,11 +34,12 @@ namespace bcm {
 
 namespace {
 
-template <int NL>
+template <int NL, int WW = NL + 2, int PP = WW * WW>
 struct Col {
   static constexpr int N2 = NL * NL, N3 = N2 * NL;
   static constexpr int CPB = NL >= 16 ? 1 : 256 / N2;  // cubes per workgroup
-  static constexpr int W = NL + 2, P = W * W, TS = NL * P;  // LDS tile of one cube
+  // LDS tile of one cube: NL planes of pitch P, rows of pitch W (NL cells and the x halos)
+  static constexpr int W = WW, P = PP, TS = NL * P;
   static constexpr int H = NL / 2, H2 = H * H, H3 = H2 * H;  // next coarser per-cube level
   static constexpr int F = face_stride(NL), FH = face_stride(H);  // face-buffer values per cube
   __device__ static int tix(int s, int i, int j, int k) { return s * TS + k * P + (j + 1) * W + (i + 1); }
@@ -129,10 +130,10 @@ __device__ __forceinline__ T halo_val(int kd, T r) {
 }
 
 // Stage face values: faces 0..3 into the LDS ring at this lane's slot, 4/5 into registers.
-template <int NL, typename T>
+template <int NL, typename T, class CL = Col<NL>>
 __device__ __forceinline__ void stage(T* tile, const T (&hv)[6], const LaneC<NL>& L, T& zlo, T& zhi) {
 #pragma unroll
-  for (int f = 0; f < 4; ++f) tile[Col<NL>::halo(L.s, f, L.i, L.j)] = hv[f];
+  for (int f = 0; f < 4; ++f) tile[CL::halo(L.s, f, L.i, L.j)] = hv[f];
   zlo = hv[4];
   zhi = hv[5];
 }
@@ -196,9 +197,9 @@ __device__ __forceinline__ void export_avg(T* xf, int c, const T* tile, const MT
   }
 }
 
-template <int NL, typename T>
+template <int NL, typename T, class CL = Col<NL>>
 __device__ __forceinline__ T nbsum(const T* tile, const T (&x)[NL], int k, int c, T zlo, T zhi) {
-  constexpr int W = Col<NL>::W;
+  constexpr int W = CL::W;
   const T zm = k > 0 ? x[k > 0 ? k - 1 : 0] : zlo;
   const T zp = k < NL - 1 ? x[k < NL - 1 ? k + 1 : NL - 1] : zhi;
   return tile[c - 1] + tile[c + 1] + tile[c - W] + tile[c + W] + zm + zp;
@@ -432,7 +433,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
   constexpr int SWEEP = !POST ? 2 : (TRI && sizeof(T) == 4 ? 1 : 0);
   // the halo-free tile of the 16^3 pre-smoother (plane pitch ZP words)
   constexpr bool ZL = !POST && NL == 16 && !ML;
-  constexpr int ZP = C::N2 + 64, TSL = ZL ? NL * ZP : C::TS;
+  // the paired form at 16^3 (the FP32 trilinear post-smoother): rows of 32 words and planes
+  // of 592, so that lanes one plane apart use other banks of each half-wavefront
+  using CT = std::conditional_t<SWEEP == 1 && NL == 16, Col<NL, 32, 592>, Col<NL>>;
+  constexpr int ZP = C::N2 + 64, TSL = ZL ? NL * ZP : CT::TS;
   // pre-smoother below the finest level: the finer level's face correction is applied here
   constexpr bool RFX = !POST && NL < 16;
   constexpr int NF = RFX ? 2 * NL : NL;  // the finer level
@@ -549,16 +553,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
       bv[k] = nb[k];
       // (a pre-smoother's first pass writes its colour before anything reads the tile, and
       // the other colour is read only after its own first pass)
-      if (POST || a.sweeps == 0) tile[ZL ? k * ZP + zc : C::tix(L.s, i, j, k)] = x[k];
+      if (POST || a.sweeps == 0) tile[ZL ? k * ZP + zc : CT::tix(L.s, i, j, k)] = x[k];
     }
     if (POST) {
       T hv[6];
 #pragma unroll
       for (int f = 0; f < 6; ++f) hv[f] = halo_val<T>(kinds[f], rf[f] + (TRI ? eh[f] : rc[f]));
-      stage<NL, T>(tile, hv, L, zlo, zhi);
+      stage<NL, T, CT>(tile, hv, L, zlo, zhi);
     } else if (!ZL) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) tile[C::halo(L.s, f, i, j)] = T(0);
+      for (int f = 0; f < 4; ++f) tile[CT::halo(L.s, f, i, j)] = T(0);
     }
     if constexpr (RFX) {
       if (rfx) {
@@ -622,8 +626,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
   #pragma unroll
         for (int k = 0; k < NL; ++k) {
           if (((i + j + k) & 1) != colour) continue;
-          const int cc = C::tix(L.s, i, j, k);
-          const T sum = nbsum<NL, T>(tile, x, k, cc, zlo, zhi);
+          const int cc = CT::tix(L.s, i, j, k);
+          const T sum = nbsum<NL, T, CT>(tile, x, k, cc, zlo, zhi);
           const T id = k == 0 ? i0 : (k == NL - 1 ? il : im);
           x[k] = (sum - h2 * bv[k]) * id;
           tile[cc] = x[k];
@@ -641,10 +645,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
   #pragma unroll
         for (int n = 0; n < NL / 2; ++n) {
           const int k0 = 2 * n, k1 = 2 * n + 1;
-          const int cc = C::tix(L.s, i, j, k0) + (odd ? C::P : 0);
+          const int cc = CT::tix(L.s, i, j, k0) + (odd ? CT::P : 0);
           const T zm = odd ? x[k0] : (k0 > 0 ? x[k0 > 0 ? k0 - 1 : 0] : zlo);
           const T zp = odd ? (k1 < NL - 1 ? x[k1 < NL - 1 ? k1 + 1 : 0] : zhi) : x[k1];
-          const T sum = tile[cc - 1] + tile[cc + 1] + tile[cc - C::W] + tile[cc + C::W] + zm + zp;
+          const T sum = tile[cc - 1] + tile[cc + 1] + tile[cc - CT::W] + tile[cc + CT::W] + zm + zp;
           const T id = odd ? (k1 == NL - 1 ? il : im) : (k0 == 0 ? i0 : im);
           const T xn = (sum - h2 * (odd ? bv[k1] : bv[k0])) * id;
           x[k0] = odd ? x[k0] : xn;
@@ -665,7 +669,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
       yb[sl] = par ? b_at(sl - 2) : b_at(sl - 1);
     }
     // LDS index of slot s: tb + s P (ZL: tz[0] + s ZP, the neighbours tz[1..4] + s ZP)
-    const int tb = C::tix(L.s, i, j, 0) - (1 + par) * C::P;
+    const int tb = CT::tix(L.s, i, j, 0) - (1 + par) * CT::P;
     const int zs = (1 + par) * ZP;
     const int tz[5] = {zc - zs, zb[0] - zs, zb[1] - zs, zb[2] - zs, zb[3] - zs};
     // one colour pass (red-black order from the zero initial guess); RD = false in the
@@ -679,7 +683,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
         if ((sl & 1) != (colour ^ 1)) continue;  // the colour's slots (the same on every lane)
         // slot 1 is a cell only on par = 0 lanes, slot NL + 1 only on par = 1 lanes
         const bool valid = sl == 1 ? par == 0 : (sl == NL + 1 ? par == 1 : true);
-        const int cc = ZL ? tz[0] + sl * ZP : tb + sl * C::P;
+        const int cc = ZL ? tz[0] + sl * ZP : tb + sl * CT::P;
         T sum = T(0);
         if constexpr (RD && ZL) {
           // a lane without a cell here reads the plane next to it (same banks), unused
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
           sum = tile[tz[1] + o] + tile[tz[2] + o] + tile[tz[3] + o] + tile[tz[4] + o] + y[sl - 1] + y[sl + 1];
         } else if constexpr (RD) {
           sum = tile[valid ? cc - 1 : 0] + tile[valid ? cc + 1 : 0] +
-                tile[valid ? cc - C::W : 0] + tile[valid ? cc + C::W : 0] + y[sl - 1] + y[sl + 1];
+                tile[valid ? cc - CT::W : 0] + tile[valid ? cc + CT::W : 0] + y[sl - 1] + y[sl + 1];
         }
         // k = sl - 1 - par: the first cell sits at slot 1 or 2, the last at NL or NL + 1
         const T id = sl == 1 ? i0 : (sl == 2 ? (par ? i0 : im)
@@ -742,7 +746,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
           const int k = 2 * kk + q2;
           const T d = k == 0 ? d0 : (k == NL - 1 ? dl : dm);
           const T sum = ZL ? nbsum_z<NL, T>(tile, zb, k * ZP, x, k)
-                           : nbsum<NL, T>(tile, x, k, C::tix(L.s, i, j, k), zlo, zhi);
+                           : nbsum<NL, T, CT>(tile, x, k, CT::tix(L.s, i, j, k), zlo, zhi);
           acc += bv[k] - (sum - d * x[k]) * ih2;
         }
         rsum[(L.s * C::H + kk) * C::N2 + L.l] = acc;
