@@ -4,8 +4,10 @@
 // Layout per workgroup (256 lanes): lane t owns one column (i, j) of a cube, k = 0..NL-1 held
 // in registers; a workgroup holds CPB = max(1, 256 / NL^2) cubes.  Only the i/j neighbours go
 // through LDS: per cube a tile of NL planes of (NL+2) x (NL+2) (the plane plus its x/y halo
-// ring); the z neighbours are the lane's own registers, with the z halo of the column in two
-// registers.  Every global access is a full plane of a cube (coalesced) or a face slab.
+// ring; at 16^3 the pre-smoother and the paired post-smoother use layouts of their own that
+// avoid LDS bank conflicts, described at kc_smooth); the z neighbours are the lane's own
+// registers, with the z halo of the column in two registers.  Every global access is a full
+// plane of a cube (coalesced) or a face slab.
 //
 // The solver kernels are persistent: a workgroup walks units of CPB cubes with stride
 // gridDim.x (a multiple of 8, so each workgroup stays on the XCD that owns its stretch of the
@@ -416,13 +418,16 @@ __device__ __forceinline__ void tri_column(const T* ct, const LaneC<NL>& L, T (&
 //   shifted: the column is copied into slots shifted by the parity (slot s = k + par + 1, the
 //            z halo in slots par and NL + par + 1), so that one colour sits in the same slots
 //            on every lane.
-// In the shifted form a lane of parity 1 works one plane below its neighbours of parity 0.
-// With the (NL+2)-wide rows that puts lanes of a wavefront on the same LDS bank.  The 16^3
-// pre-smoother of single-level meshes therefore keeps a tile without halo (ZL): rows of NL
-// cells, planes of NL^2 cells followed by 64 zeros, a plane pitch that is a multiple of 64
-// words.  A lane on a cube face reads one of the zeros instead of its halo cell (the halo of a
-// pre-smoother is zero), picked so that its bank is one the other lanes of the wavefront leave
-// free.  Every access of the sweeps then hits 64 distinct banks (32 per half-wavefront).
+// In the shifted and paired forms a lane of parity 1 works one plane away from its neighbours
+// of parity 0.  With (NL+2)-wide rows that puts lanes of a half-wavefront (the 32 lanes whose
+// 32-bit LDS accesses are served together) on the same bank.  At 16^3:
+//   * the pre-smoother of single-level meshes keeps a tile without halo (ZL): rows of NL cells,
+//     planes of NL^2 cells followed by 64 zeros, a plane pitch that is a multiple of 64 words.
+//     A lane on a cube face reads one of the zeros instead of its halo cell (the halo of a
+//     pre-smoother is zero), picked so that its bank is one the other lanes leave free; every
+//     access of the sweeps then hits distinct banks;
+//   * the paired post-smoother keeps its halo ring in rows of 32 words and planes of 592
+//     (16 mod 64 words), which puts the two parities on different banks.
 // ------------------------------------------------------------------------------------------
 template <typename T, int NL, bool POST, bool ML, bool TRI = false>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothArgs<T> a) {

@@ -107,8 +107,11 @@ def test_split_graph_multigrid_matches_oracle(name, precision):
 @pytest.mark.parametrize("name", ["channel_n16", "multilevel_small_n4"])
 @pytest.mark.parametrize("opts", [dict(coarse_solver=0, max_iter=200), dict(krylov=0, max_iter=200),
                                   dict(coarse_cycles=2), dict(pre_sweeps=1, post_sweeps=3),
+                                  dict(pre_sweeps=0, post_sweeps=2, max_iter=200),
+                                  dict(pre_sweeps=3, post_sweeps=1),
                                   dict(prolong=0), dict(krylov=2), dict(check_every=3)],
                          ids=["paper_cg", "vcycle_iteration", "two_graph_cycles", "sweeps_1_3",
+                              "sweeps_0_2", "sweeps_3_1",
                               "constant_prolongation", "standard_pcg", "checks_every_3"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solver_variants_match_oracle(name, opts, precision):
