@@ -204,8 +204,12 @@ int read_scalars(bcm_plan* P, Scalars* host, hipStream_t s) {
 }
 
 int finalize(bcm_plan* P, int op, int which0, int which1, int nparts, int first, hipStream_t s) {
+  // the two recurrences in the middle of a Krylov iteration are never read by the host before
+  // the next finalize: they skip the copy to the pinned mirror and its system-scope fence
+  const bool publish = P->mirror && op != OP_ZRZQ && op != OP_PQ;
   FinalizeArgs a{P->at<double>(P->o_part[which0]), which1 >= 0 ? P->at<double>(P->o_part[which1]) : nullptr,
-                 nparts, P->at<Scalars>(P->o_sc), op, first, P->mirror, P->mirror ? ++P->mirror_seq : 0u};
+                 nparts, P->at<Scalars>(P->o_sc), op, first, publish ? P->mirror : nullptr,
+                 publish ? ++P->mirror_seq : 0u};
   HIPCHK(timed(P, cls_of("finalize", 0), s, [&] { return launch_finalize(a, s); }), "k_finalize");
   return BCM_OK;
 }
