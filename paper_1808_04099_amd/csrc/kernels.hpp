@@ -114,6 +114,7 @@ struct IrArgs {         // p += dscale * d (when d != nullptr); export faces of 
   const T* d;
   double* pf_out;
   double dscale;
+  int p_zero;           // p is zero and not read (p = dscale * d)
 };
 
 template <typename T, typename TO>

@@ -1047,8 +1047,13 @@ __global__ __launch_bounds__(256) void kc_ir(IrArgs<T> a) {
     const int c = unit_cube<NL>(a.g, u, L.s);
     const int ce = c < 0 ? 0 : c;
     double p[NL];
+    if (a.p_zero) {
 #pragma unroll
-    for (int k = 0; k < NL; ++k) p[k] = ld_nt(a.p + (size_t)ce * C::N3 + k * C::N2 + L.l);
+      for (int k = 0; k < NL; ++k) p[k] = 0.0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) p[k] = ld_nt(a.p + (size_t)ce * C::N3 + k * C::N2 + L.l);
+    }
     if (a.d) {
       T d[NL];
 #pragma unroll

@@ -521,7 +521,15 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
   int st = BCM_OK;
   int outer = 0;
   bool faces_ok = false;  // the face buffer holds the faces of the current p
-  if (!use_guess) HIPCHK(fill<double>(p, P->cells, s), "zero fill");
+  // Without a guess p starts at zero.  The mixed path never reads p before its first
+  // refinement update, which then writes p = d instead of adding d to a zero-filled p; an exit
+  // before that update fills p (p_unwritten).
+  bool p_unwritten = !use_guess && P->inner32;
+  if (!use_guess && !P->inner32) HIPCHK(fill<double>(p, P->cells, s), "zero fill");
+  auto fail = [&](int e) {
+    if (p_unwritten && fill<double>(p, P->cells, s) == hipSuccess) p_unwritten = false;
+    return e;
+  };
   double bb = 0.0, rr = 0.0;
   const double tol2 = o.tol * o.tol;
   bool converged = false, stagnated = false;
@@ -582,15 +590,16 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
     for (outer = 0; outer < o.max_outer; ++outer) {
       float* r32 = P->at<float>(P->o_r);
       const double* pg = (use_guess || outer) ? p : nullptr;
-      if ((st = residual64<float>(P, pg, b, r32, rscale, s, faces_ok))) return st;
+      if ((st = residual64<float>(P, pg, b, r32, rscale, s, faces_ok))) return fail(st);
       faces_ok = pg != nullptr;
-      if ((st = read_scalars(P, &hs, s))) return st;
+      if ((st = read_scalars(P, &hs, s))) return fail(st);
       unchecked = false;
       if (outer == 0) bb = hs.bb;
       rr = hs.rr;
-      if (!std::isfinite(rr) || !std::isfinite(bb)) return nonfinite();
+      if (!std::isfinite(rr) || !std::isfinite(bb)) return fail(nonfinite());
       if (bb == 0.0) {
         HIPCHK(fill<double>(p, P->cells, s), "zero fill");
+        p_unwritten = false;
         faces_ok = false;
         rr = 0.0;
         converged = true;
@@ -610,7 +619,7 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
       if (outer == 0 && !(rscale > 0 && std::fabs(std::log10(rr / vol)) < 20)) {
         // first pass unscaled and far from unit size: redo the conversion with the true norm
         rscale = 1.0 / std::sqrt(rr / vol);
-        if ((st = residual64<float>(P, pg, b, r32, rscale, s, faces_ok))) return st;
+        if ((st = residual64<float>(P, pg, b, r32, rscale, s, faces_ok))) return fail(st);
       }
       float* d = P->at<float>(P->o_d);
       // reduce the residual by inner_tol, or only by what is still missing to reach tol
@@ -619,13 +628,18 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
       const double red_target = std::max(o.inner_tol, std::min(need, 0.1));
       const double thr = red_target * red_target * rr * rscale * rscale;
       if ((st = krylov<float>(P, d, true, thr, o.max_iter, 1.0 / (rscale * std::sqrt(bb)), log, &hs, s)))
-        return st;
-      IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale};
+        return fail(st);
+      IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale, p_unwritten ? 1 : 0};
       HIPCHK(timed(P, cls_of("ir", 0), s, [&] { return launch_ir<float>(P->n, ia, s); }), "kc_ir");
+      p_unwritten = false;
       faces_ok = true;  // kc_ir exports the faces of the updated p
       unchecked = true;
       const double rr_est = hs.rr / (rscale * rscale);
       if (rr_est > 0 && std::isfinite(rr_est)) rscale = 1.0 / std::sqrt(rr_est / vol);
+    }
+    if (p_unwritten) {  // converged without a refinement step (a tolerance of 1 or more)
+      HIPCHK(fill<double>(p, P->cells, s), "zero fill");
+      p_unwritten = false;
     }
     if (unchecked) {  // the last refinement step has not been evaluated yet
       if ((st = residual64<float>(P, p, b, P->at<float>(P->o_r), rscale, s, faces_ok))) return st;

@@ -18,6 +18,25 @@ pytestmark = [pytest.mark.gpu, requires_gpu]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["zero_rhs", "tol_above_one"])
+def test_solve_without_an_update_returns_zero_pressure(precision, case):
+    """Without a guess the pressure starts at zero.  A solve that ends before its first update
+    (a zero right-hand side, or a tolerance the zero pressure already meets) returns exactly
+    zero, whatever the output buffer held before (here NaN)."""
+    m = uniform_mesh((2, 2, 1), 0.5, 8, CHANNEL_BC)
+    plan = plan_for(m, precision, tol=2.0) if case == "tol_above_one" else plan_for(m, precision)
+    b = np.zeros(m.n_cells) if case == "zero_rhs" else np.random.default_rng(2).standard_normal(m.n_cells)
+    p0 = dev(np.full(m.n_cells, np.nan))
+    p, rep = plan.poisson_solve(dev(b), p=p0, use_guess=False)
+    assert rep.status == 0 and rep.n_inner == 0
+    if case == "zero_rhs":
+        assert rep.final_rel_res == 0.0
+    else:
+        assert abs(rep.final_rel_res - 1.0) <= 1e-6
+    assert np.array_equal(host(p), np.zeros(m.n_cells))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_zero_right_hand_side_gives_zero_pressure(precision):
     m = uniform_mesh((2, 2, 1), 0.5, 8, CHANNEL_BC)
     plan = plan_for(m, precision)
