@@ -115,6 +115,11 @@ struct IrArgs {         // p += dscale * d (when d != nullptr); export faces of 
   double* pf_out;
   double dscale;
   int p_zero;           // p is zero and not read (p = dscale * d)
+  // the inner solve's last x update, applied here (when pdir != nullptr): d + alpha pdir in
+  // T precision, with d taken as zero (not read) when d_zero
+  const T* pdir;
+  const Scalars* sc;
+  int d_zero;
 };
 
 template <typename T, typename TO>

@@ -1056,8 +1056,18 @@ __global__ __launch_bounds__(256) void kc_ir(IrArgs<T> a) {
     }
     if (a.d) {
       T d[NL];
+      if (a.d_zero) {
 #pragma unroll
-      for (int k = 0; k < NL; ++k) d[k] = ld_nt(a.d + (size_t)ce * C::N3 + k * C::N2 + L.l);
+        for (int k = 0; k < NL; ++k) d[k] = T(0);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) d[k] = ld_nt(a.d + (size_t)ce * C::N3 + k * C::N2 + L.l);
+      }
+      if (a.pdir) {  // the inner solve's last x update (the arithmetic of k_update)
+        const T al = T(a.sc->alpha);
+#pragma unroll
+        for (int k = 0; k < NL; ++k) d[k] = d[k] + al * ld_nt(a.pdir + (size_t)ce * C::N3 + k * C::N2 + L.l);
+      }
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
         p[k] += a.dscale * double(d[k]);

@@ -388,9 +388,12 @@ constexpr double kStallFactor = 0.99;  // progress = the residual norm falls bel
 // residual and x the accumulator (x_zero: x starts at zero and is not read before its first
 // update).  Stops when the V-weighted <r, r> <= thr (recurrence).
 // hist_scale converts sqrt(<r,r>) to the reported relative residual.
+// defer: on a normal return the last pending x update is not launched but handed to the
+// caller in *defer (defer->p != nullptr), which must apply it (the mixed path folds it into
+// the refinement update).
 template <typename T>
 int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist_scale, SolveLog& log,
-           Scalars* hs, hipStream_t s) {
+           Scalars* hs, hipStream_t s, UpdateArgs<T>* defer = nullptr) {
   const int NL = P->n;
   const int nparts = partials_of(NL, P->nc);
   T* r = P->at<T>(P->o_r);
@@ -440,6 +443,10 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   };
   auto finish = [&](int st) {  // every exit: no x update left behind
     int e = join_x();
+    if (!e && !st && defer && pending) {  // the caller applies it
+      *defer = ux;
+      pending = false;
+    }
     if (!e) e = start_x(false, nullptr);  // nothing left to run beside: on the caller's stream
     return st ? st : e;
   };
@@ -627,9 +634,12 @@ int poisson(bcm_plan* P, const double* b, double* p, bool use_guess, bcm_report*
       const double need = 0.3 * o.tol * std::sqrt(bb / rr);
       const double red_target = std::max(o.inner_tol, std::min(need, 0.1));
       const double thr = red_target * red_target * rr * rscale * rscale;
-      if ((st = krylov<float>(P, d, true, thr, o.max_iter, 1.0 / (rscale * std::sqrt(bb)), log, &hs, s)))
+      UpdateArgs<float> last{};  // the inner solve's last x update, folded into kc_ir
+      if ((st = krylov<float>(P, d, true, thr, o.max_iter, 1.0 / (rscale * std::sqrt(bb)), log, &hs, s,
+                              &last)))
         return fail(st);
-      IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale, p_unwritten ? 1 : 0};
+      IrArgs<float> ia{geom(P, P->n), p, d, P->at<double>(P->o_pf), 1.0 / rscale, p_unwritten ? 1 : 0,
+                       last.p, last.sc, last.p ? last.x_zero : 0};
       HIPCHK(timed(P, cls_of("ir", 0), s, [&] { return launch_ir<float>(P->n, ia, s); }), "kc_ir");
       p_unwritten = false;
       faces_ok = true;  // kc_ir exports the faces of the updated p
