@@ -47,7 +47,7 @@ def alg_bytes_per_cell(cls, s, f, body=1.0):
         "update": 3 * s,                 # read r, q; write r
         "xupdate": 3 * s,                # read x, p; write x (beside the next V-cycle)
         "resid64": 16 + s,               # read p, b (FP64); write r
-        "ir": 8 + s + 8,                 # read p, d; write p
+        "ir": 8 + 2 * s + 8,             # read p, d and the inner solve's last direction; write p
         "force": f + 6 * f * body,       # read alpha; in body cubes read u~ (3), write u* (3)
         "div": 3 * f + 8,                # read u* (3); write b
         "correct": 8 + 6 * f,            # read p, u* (3); write u_new (3)
