@@ -177,10 +177,9 @@ __device__ __forceinline__ void export_col(T* xf, int c, const T (&x)[NL], int i
 // 2x2 means of the face slabs on faces that border a coarser cube (see face_stride), from the
 // cube's values in the LDS tile; summed in the order (0,0), (1,0), (0,1), (1,1) of the two
 // tangential axes.  Lanes of each cube slot with l < (NL/2)^2 compute one mean per face.
-template <int NL, typename T, class MT>
+template <int NL, typename T, class MT, class C = Col<NL>>
 __device__ __forceinline__ void export_avg(T* xf, int c, const T* tile, const MT& m,
                                            const LaneC<NL>& L) {
-  using C = Col<NL>;
   if (L.l >= C::H2) return;
   const int A = L.l % C::H, B = L.l / C::H;
   T* base = xf + (size_t)c * C::F + 6 * C::N2;
@@ -433,9 +432,9 @@ template <typename T, int NL, bool POST, bool ML, bool TRI = false>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
-  // sweep form (same update order): shifted columns before restriction; with the trilinear
-  // prolongation the paired form in FP32 (fewer registers), else the masked form
-  constexpr int SWEEP = !POST ? 2 : (TRI && sizeof(T) == 4 ? 1 : 0);
+  // sweep form (same update order): shifted columns before restriction; in FP32 after the
+  // trilinear prolongation or at 16^3 the paired form (fewer registers), else the masked form
+  constexpr int SWEEP = !POST ? 2 : (sizeof(T) == 4 && (TRI || NL == 16) ? 1 : 0);
   // the halo-free tile of the 16^3 pre-smoother (plane pitch ZP words)
   constexpr bool ZL = !POST && NL == 16 && !ML;
   // the paired form at 16^3 (the FP32 trilinear post-smoother): rows of 32 words and planes
@@ -737,7 +736,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothA
         }
       }
       export_col<NL, T>(a.xf_out, c, x, i, j);
-      if (ML) export_avg<NL, T>(a.xf_out, c, tile, m, L);
+      if (ML) export_avg<NL, T, MetaRO, CT>(a.xf_out, c, tile, m, L);
     }
     if (!POST && a.bc) {
       // residual with the halo the sweeps used (zero across cube faces), summed over the 2x2x2
