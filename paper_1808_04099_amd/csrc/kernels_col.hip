@@ -429,7 +429,7 @@ __device__ __forceinline__ void tri_column(const T* ct, const LaneC<NL>& L, T (&
 //     (16 mod 64 words), which puts the two parities on different banks.
 // ------------------------------------------------------------------------------------------
 template <typename T, int NL, bool POST, bool ML, bool TRI = false>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kc_smooth(SmoothArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
   // sweep form (same update order): shifted columns before restriction; in FP32 after the
