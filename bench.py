@@ -35,6 +35,8 @@ def alg_bytes_per_cell(cls, s, f, body=1.0):
     some nonzero volume fraction (the only ones the 16^3 forcing kernel reads and stores)."""
     return {
         "presmooth16": 2 * s + s / 8,    # read b; write x and the restricted residual
+        "preupd16": 4 * s + s / 8,       # the same with the previous step's r update fused in:
+                                         # read r, q; write r, x and the restricted residual
         "presmooth8": 3 * s + s / 8,     # below the finest level b is completed (its cross-cube
         "presmooth4": 3 * s + s / 8,     # terms) and written back as well
         "presmooth2": 3 * s + s / 8,
@@ -62,7 +64,7 @@ def level_cells(cls, n_cells, n):
     return n_cells * (int(digits) / n) ** 3
 
 
-CLASSES = ("presmooth16", "postsmooth16", "apply16", "update", "xupdate", "resid64", "ir",
+CLASSES = ("presmooth16", "preupd16", "postsmooth16", "apply16", "update", "xupdate", "resid64", "ir",
            "coarse", "force", "div", "correct", "presmooth8", "postsmooth8", "presmooth4",
            "postsmooth4", "presmooth2", "postsmooth2", "restrict2", "finalize")
 

@@ -58,6 +58,12 @@ struct SmoothArgs {
   const T* q_dot;
   double* part_zr;
   double* part_zq;
+  // pre-smoother of level 0: the previous Krylov step's r -= alpha q applied to b (= r) as it
+  // is loaded and stored back, with the partial sums of <r, r>_V (one per workgroup, zeros
+  // up to fine_grid(units)); upd_q == nullptr: b is used as it is
+  const T* upd_q;
+  const Scalars* upd_sc;
+  double* part_rr;
 };
 
 template <typename T>

@@ -428,7 +428,8 @@ __device__ __forceinline__ void tri_column(const T* ct, const LaneC<NL>& L, T (&
 //   * the paired post-smoother keeps its halo ring in rows of 32 words and planes of 592
 //     (16 mod 64 words), which puts the two parities on different banks.
 // ------------------------------------------------------------------------------------------
-template <typename T, int NL, bool POST, bool ML, bool TRI = false>
+// UPD (pre-smoother of level 0): the previous Krylov step's r update is fused in (upd_q).
+template <typename T, int NL, bool POST, bool ML, bool TRI = false, bool UPD = false>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void kc_smooth(SmoothArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
@@ -471,12 +472,17 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
   T rr[RFX ? 24 : 1];
   int rk[RFX ? 6 : 1];
   const bool rfx = RFX && a.rfx != nullptr;
+  // pre-smoother of level 0: the r update of the previous Krylov step, fused in
+  constexpr bool upd = !POST && UPD;
+  const T ual = upd ? T(a.upd_sc->alpha) : T(0);
+  T nq[upd ? NL : 1];
   auto fetch = [&](int cc) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const size_t g = (size_t)cc * C::N3 + k * C::N2 + L.l;
       nb[k] = ld_nt(a.b + g);
       if (POST) nx[k] = ld_nt(a.x + g);
+      if constexpr (upd) nq[k] = ld_nt(a.upd_q + g);
     }
     if constexpr (RFX) {
       if (rfx) {
@@ -531,7 +537,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
     if (u + G < U) coarse_ent<NL>(a.nb27, a.g.n_cubes, u + G, entn);
   }
   if (PF && u < U) fetch(c < 0 ? 0 : c);
-  double zr = 0.0, zq = 0.0;
+  double zr = 0.0, zq = 0.0, rrs = 0.0;
   while (u < U) {
     const int ce = c < 0 ? 0 : c;
     if (!PF) fetch(ce);  // FP64 at 16^3: no prefetch (registers go to occupancy)
@@ -550,6 +556,18 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
       tri_column<NL, T>(ctile, L, e, eh);
 #pragma unroll
       for (int k = 0; k < NL; ++k) x[k] = nx[k] + e[k];
+    }
+    if constexpr (upd) {
+      // r -= alpha q (the arithmetic of k_update), stored back, and its norm
+      MetaRO& mu = meta_ro(a.g.meta, ce);
+      double rq = 0.0;
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        nb[k] = nb[k] - ual * nq[k];
+        rq += double(nb[k]) * double(nb[k]);
+        if (c >= 0) st_nt(const_cast<T*>(a.b) + (size_t)c * C::N3 + k * C::N2 + L.l, nb[k]);
+      }
+      if (c >= 0) rrs += mu.vol * rq;
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
@@ -780,6 +798,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
         a.part_zq[blockIdx.x] = t1;
         zero_tail(a.part_zq, U);
       }
+    }
+  }
+  if constexpr (upd) {
+    const double t0 = block_sum(rrs, red);
+    if (threadIdx.x == 0) {
+      a.part_rr[blockIdx.x] = t0;
+      zero_tail(a.part_rr, U);
     }
   }
 }
@@ -1356,9 +1381,11 @@ hipError_t launchc_smooth(int NL, const SmoothArgs<T>& a, hipStream_t s) {
   BCM_COL_NL(NL, {
     constexpr int cpb = Col<NLC>::CPB;
     if (a.g.multilevel) {
+      if (a.zero_init && a.upd_q) return launch_col(kc_smooth<T, NLC, false, true, false, true>, cpb, a, s);
       if (a.zero_init) return launch_col(kc_smooth<T, NLC, false, true>, cpb, a, s);
       return launch_col(kc_smooth<T, NLC, true, true>, cpb, a, s);
     }
+    if (a.zero_init && a.upd_q) return launch_col(kc_smooth<T, NLC, false, false, false, true>, cpb, a, s);
     if (a.zero_init) return launch_col(kc_smooth<T, NLC, false, false>, cpb, a, s);
     if (a.nb27) return launch_col(kc_smooth<T, NLC, true, false, true>, cpb, a, s);
     return launch_col(kc_smooth<T, NLC, true, false>, cpb, a, s);

@@ -47,7 +47,7 @@ const char* const kTimerNames[] = {"presmooth16", "presmooth8", "presmooth4", "p
                                    "apply4", "apply2", "update", "resid64", "ir", "coarse",
                                    "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
                                    "export", "xupdate", "momentum", "momentum_start", "ib", "codec",
-                                   nullptr};
+                                   "preupd16", "preupd8", "preupd4", "preupd2", nullptr};
 
 int level_index(int NL) { return NL == 16 ? 0 : NL == 8 ? 1 : NL == 4 ? 2 : 3; }
 
@@ -287,11 +287,17 @@ struct VLevels {
 // fused in.  Its cross-cube terms need the neighbours' smoothed faces, so the next level's
 // pre-smoother adds them (it reads nothing across faces itself: its iterate starts at zero),
 // and kc_rfix only after the last such level.
+// upd (level 0): the previous Krylov step's r update, applied by this launch to b (= r).
 template <typename T>
-int presmooth(bcm_plan* P, int l, hipStream_t s) {
+int presmooth(bcm_plan* P, int l, hipStream_t s, const UpdateArgs<T>* upd = nullptr) {
   const VLevels<T> V{P};
   const int NL = P->n >> l;
   SmoothArgs<T> sa{};
+  if (upd) {
+    sa.upd_q = upd->q;
+    sa.upd_sc = upd->sc;
+    sa.part_rr = P->at<double>(P->o_part[0]);
+  }
   sa.g = geom(P, NL);
   sa.x = V.X(l);
   sa.b = V.B(l);
@@ -305,7 +311,8 @@ int presmooth(bcm_plan* P, int l, hipStream_t s) {
     sa.b_fixed = V.B(l);
     sa.rfx_hscale = geom(P, NL * 2).hscale;
   }
-  HIPCHK(timed(P, cls_of("presmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }), "kc_smooth (pre)");
+  HIPCHK(timed(P, cls_of(upd ? "preupd" : "presmooth", NL), s, [&] { return launch_smooth<T>(NL, sa, s); }),
+         "kc_smooth (pre)");
   return BCM_OK;
 }
 
@@ -313,20 +320,30 @@ int presmooth(bcm_plan* P, int l, hipStream_t s) {
 // red-black Gauss-Seidel, then the one-cell-per-cube level (cube-graph multigrid, or the
 // paper's CG with coarse_solver 0).  At level 0 the final smoothing also accumulates <z, r>
 // and (if q_dot) <z, q>.
-template <typename T, class Hook>
-int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s, Hook&& before_coarse) {
+//
+// upd: the previous Krylov step's r update, applied by the level-0 pre-smoother (which needs
+// nlev >= 2), after which after_pre0(stop) runs (the convergence check); stop = true ends the
+// V-cycle there.
+template <typename T, class Hook, class After>
+int vcycle(bcm_plan* P, const T* q_dot, hipStream_t s, Hook&& before_coarse, const UpdateArgs<T>* upd,
+           After&& after_pre0, bool& stop) {
   const int L = P->nlev;
   const VLevels<T> V{P};
   auto X = [&](int l) { return V.X(l); };
   auto B = [&](int l) { return V.B(l); };
   auto F = [&](int ab, int l) { return V.F(ab, l); };
   const bcm_solver_opts& o = P->o;
+  stop = false;
   for (int l = 0; l < L - 1; ++l) {
     const int NL = P->n >> l;
-    if (const int st = presmooth<T>(P, l, s)) return st;
+    if (const int st = presmooth<T>(P, l, s, l == 0 ? upd : nullptr)) return st;
     if (l == L - 2) {
       RestrictFixArgs<T> ra{geom(P, NL), F(0, l), B(l + 1)};
       HIPCHK(timed(P, cls_of("restrict", NL), s, [&] { return launchc_rfix<T>(NL, ra, s); }), "kc_rfix");
+    }
+    if (l == 0) {
+      if (const int st = after_pre0(stop)) return st;
+      if (stop) return BCM_OK;
     }
   }
   if (P->graph && P->g_split > 0) {
@@ -454,10 +471,60 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   // residual norm seen so far end the solve early (the iterate stays valid)
   double best_rr = HUGE_VAL;
   int stall = 0;
+  // The r update r -= alpha q of iteration it is applied by the first pre-smoother of V-cycle
+  // it + 1 (which reads r anyway), and the convergence check after it sits between that
+  // pre-smoother and the rest of the V-cycle; a converged solve drops the rest.  After the
+  // last iteration, or without a per-cube level to smooth (nlev < 2), it runs on its own.
+  const bool fuse = P->nlev >= 2;
+  UpdateArgs<T> ur{};
+  bool r_pending = false;
+  // <r, r> of the update of iteration it (partials: nrr), and the convergence checks every
+  // check_every iterations and at the last one
+  auto check = [&](int it, int nrr, bool& stop) -> int {
+    stop = false;
+    if (const int st = finalize(P, OP_RR, 0, -1, nrr, 0, s)) return st;
+    log.iters++;
+    if ((it + 1) % P->o.check_every != 0 && it + 1 < max_iter) return BCM_OK;
+    if (const int st = read_scalars(P, hs, s)) return st;
+    if (!std::isfinite(hs->rr)) {
+      set_error("non-finite residual in the Krylov iteration");
+      return BCM_ERR_NONFINITE;
+    }
+    log.push(std::sqrt(std::max(hs->rr, 0.0)) * hist_scale);
+    if (hs->rr <= thr) {
+      stop = true;
+    } else if (hs->rr < kStallFactor * kStallFactor * best_rr) {
+      best_rr = hs->rr;
+      stall = 0;
+    } else if (++stall >= kStallChecks) {
+      log.stalled = true;
+      stop = true;
+    }
+    return BCM_OK;
+  };
+  // the pending r update on its own (per-cube partials)
+  auto update_alone = [&](int it, bool& stop) -> int {
+    r_pending = false;
+    HIPCHK(timed(P, cls_of("update", 0), s, [&] { return launch_update<T>(ur, s); }), "k_update");
+    return check(it, P->nc, stop);
+  };
   for (int it = 0; it < max_iter; ++it) {
+    bool stop = false;
+    if (r_pending && !fuse) {
+      if (const int st = update_alone(it - 1, stop)) return finish(st);
+      if (stop) break;
+    }
     int st = vcycle<T>(P, (flex && it > 0) ? q : nullptr, s,
-                       [&](CoarseMGArgs<T>* carrier) { return start_x(true, carrier); });
+                       [&](CoarseMGArgs<T>* carrier) { return start_x(true, carrier); },
+                       r_pending ? &ur : nullptr,
+                       [&](bool& stop_) -> int {
+                         if (!r_pending) return BCM_OK;
+                         r_pending = false;
+                         return check(it - 1, nparts, stop_);
+                       },
+                       stop);
     if (st) return finish(st);
+    if (stop) break;
     if ((st = finalize(P, OP_ZRZQ, 0, (flex && it > 0) ? 1 : -1, nparts, !fcg || it == 0, s))) return finish(st);
     if ((st = join_x())) return finish(st);
     ApplyArgs<T> aa{geom(P, NL), z, P->at<T>(P->o_zf[1]), p, P->at<T>(P->o_pfk[P->pf_cur]),
@@ -469,30 +536,16 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     if (!fcg) {  // stationary iteration: x += z, r -= A z  (alpha = 1)
       if ((st = finalize(P, OP_PQ, 0, -1, nparts, 0, s))) return finish(st);  // alpha = zr / zr
     }
-    UpdateArgs<T> ua{P->at<const CubeMeta>(P->o_meta), P->nc, NL * NL * NL, x, p, r, q,
-                     P->at<const Scalars>(P->o_sc), P->at<double>(P->o_part[0]), x_zero && it == 0, 1};
-    HIPCHK(timed(P, cls_of("update", 0), s, [&] { return launch_update<T>(ua, s); }), "k_update");
-    ux = ua;
+    ur = UpdateArgs<T>{P->at<const CubeMeta>(P->o_meta), P->nc, NL * NL * NL, x, p, r, q,
+                       P->at<const Scalars>(P->o_sc), P->at<double>(P->o_part[0]), x_zero && it == 0, 1};
+    r_pending = true;
+    ux = ur;
     ux.part_sel = 2;
     pending = true;
-    if ((st = finalize(P, OP_RR, 0, -1, P->nc, 0, s))) return finish(st);
-    log.iters++;
-    // convergence checks every check_every iterations and at the last one
-    if ((it + 1) % P->o.check_every != 0 && it + 1 < max_iter) continue;
-    if ((st = read_scalars(P, hs, s))) return finish(st);
-    if (!std::isfinite(hs->rr)) {
-      set_error("non-finite residual in the Krylov iteration");
-      return finish(BCM_ERR_NONFINITE);
-    }
-    log.push(std::sqrt(std::max(hs->rr, 0.0)) * hist_scale);
-    if (hs->rr <= thr) break;
-    if (hs->rr < kStallFactor * kStallFactor * best_rr) {
-      best_rr = hs->rr;
-      stall = 0;
-    } else if (++stall >= kStallChecks) {
-      log.stalled = true;
-      break;
-    }
+  }
+  if (r_pending) {  // the last iteration's r update
+    bool stop = false;
+    if (const int st = update_alone(max_iter - 1, stop)) return finish(st);
   }
   return finish(BCM_OK);
 }

@@ -92,15 +92,42 @@ def test_unreachable_tolerance_stagnates(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_sampled_kernel_timing(precision):
-    """bcm_timing_sample(every): one launch in each run of `every` is timed.  The r update runs
-    once per Krylov iteration, so ceil(n_inner / every) of its launches carry events."""
+    """bcm_timing_sample(every): one launch in each run of `every` is timed.  The operator apply
+    runs once per Krylov iteration, so ceil(n_inner / every) of its launches carry events."""
     m, b = _problem()
     plan = plan_for(m, precision, tol=1e-10)
     for every in (1, 3):
-        plan.timing_enable("update", every)
+        plan.timing_enable("apply8", every)
         p, rep = plan.poisson_solve(dev(b))
         n, ms = plan.timing_read()
         plan.timing_enable(None)
         log(f"  {precision}: every {every}: {n} timed of {rep.n_inner} launches, {ms:.3f} ms")
         assert rep.status == OK
         assert n == -(-rep.n_inner // every) and ms > 0.0
+
+
+def test_r_update_rides_in_the_next_first_presmoother():
+    """The r update of each Krylov iteration is applied by the first pre-smoother of the next
+    V-cycle (timer class preupd8), after which the convergence check runs: an FP64 solve that
+    converges has as many such launches as iterations and no separate r update; one stopped by
+    max_iter runs its last update on its own."""
+    m, b = _problem()
+    plan = plan_for(m, "fp64", tol=1e-10)
+    counts = {}
+    for cls in ("preupd8", "update", "presmooth8"):
+        plan.timing_enable(cls)
+        p, rep = plan.poisson_solve(dev(b))
+        counts[cls] = plan.timing_read()[0]
+        plan.timing_enable(None)
+        assert rep.status == OK
+    log(f"  converged: {counts}, n_inner {rep.n_inner}")
+    assert counts == {"preupd8": rep.n_inner, "update": 0, "presmooth8": 1}
+    _check_report(m, b, host(p), rep)
+    plan = plan_for(m, "fp64", max_iter=3, max_outer=1)
+    plan.timing_enable("update")
+    p, rep = plan.poisson_solve(dev(b))
+    n_alone = plan.timing_read()[0]
+    plan.timing_enable(None)
+    log(f"  max_iter 3: status {rep.status}, {n_alone} separate r update(s)")
+    assert rep.status == NOT_CONVERGED and rep.n_inner == 3 and n_alone == 1
+    _check_report(m, b, host(p), rep)
