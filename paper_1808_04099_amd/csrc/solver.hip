@@ -475,9 +475,13 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   // it + 1 (which reads r anyway), and the convergence check after it sits between that
   // pre-smoother and the rest of the V-cycle; a converged solve drops the rest.  After the
   // last iteration, or without a per-cube level to smooth (nlev < 2), it runs on its own.
+  // A fused launch whose check ends the solve does its pre-smoothing for nothing, so when the
+  // residual's last reduction factor predicts convergence at the next check (with checks every
+  // iteration), that update runs on its own instead.
   const bool fuse = P->nlev >= 2;
   UpdateArgs<T> ur{};
   bool r_pending = false;
+  double rr_a = -1.0, rr_b = -1.0;  // the last two checked <r, r> (rr_b the latest)
   // <r, r> of the update of iteration it (partials: nrr), and the convergence checks every
   // check_every iterations and at the last one
   auto check = [&](int it, int nrr, bool& stop) -> int {
@@ -491,6 +495,8 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
       return BCM_ERR_NONFINITE;
     }
     log.push(std::sqrt(std::max(hs->rr, 0.0)) * hist_scale);
+    rr_a = rr_b;
+    rr_b = hs->rr;
     if (hs->rr <= thr) {
       stop = true;
     } else if (hs->rr < kStallFactor * kStallFactor * best_rr) {
@@ -510,7 +516,11 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   };
   for (int it = 0; it < max_iter; ++it) {
     bool stop = false;
-    if (r_pending && !fuse) {
+    bool alone = r_pending && !fuse;
+    if (r_pending && fuse && P->o.check_every == 1 && rr_a > 0.0 && rr_b > 0.0 &&
+        rr_b * (rr_b / rr_a) <= 3.0 * thr)
+      alone = true;  // predicted to converge at this check
+    if (alone) {
       if (const int st = update_alone(it - 1, stop)) return finish(st);
       if (stop) break;
     }

@@ -108,9 +108,10 @@ def test_sampled_kernel_timing(precision):
 
 def test_r_update_rides_in_the_next_first_presmoother():
     """The r update of each Krylov iteration is applied by the first pre-smoother of the next
-    V-cycle (timer class preupd8), after which the convergence check runs: an FP64 solve that
-    converges has as many such launches as iterations and no separate r update; one stopped by
-    max_iter runs its last update on its own."""
+    V-cycle (timer class preupd8), after which the convergence check runs, except where the
+    last reduction factor predicts convergence at that check (then it runs on its own, and a
+    plain pre-smoother follows if the solve goes on): every update is one or the other.  A solve
+    stopped by max_iter runs its last update on its own."""
     m, b = _problem()
     plan = plan_for(m, "fp64", tol=1e-10)
     counts = {}
@@ -121,7 +122,10 @@ def test_r_update_rides_in_the_next_first_presmoother():
         plan.timing_enable(None)
         assert rep.status == OK
     log(f"  converged: {counts}, n_inner {rep.n_inner}")
-    assert counts == {"preupd8": rep.n_inner, "update": 0, "presmooth8": 1}
+    assert counts["preupd8"] + counts["update"] == rep.n_inner
+    assert counts["preupd8"] >= rep.n_inner - 3 and counts["update"] >= 1
+    # the first V-cycle's, and one after each update on its own that did not end the solve
+    assert counts["presmooth8"] in (counts["update"], counts["update"] + 1)
     _check_report(m, b, host(p), rep)
     plan = plan_for(m, "fp64", max_iter=3, max_outer=1)
     plan.timing_enable("update")
