@@ -47,6 +47,7 @@ def alg_bytes_per_cell(cls, s, f, body=1.0):
         "restrict2": s / 4,              # the one-cell-per-cube residual's cross-cube terms
         "apply16": 4 * s,                # read z, p; write p, q
         "update": 3 * s,                 # read r, q; write r
+        "rprobe": 2 * s,                 # read r, q (<r - alpha q, r - alpha q> only)
         "xupdate": 3 * s,                # read x, p; write x (beside the next V-cycle)
         "resid64": 16 + s,               # read p, b (FP64); write r
         "ir": 8 + 2 * s + 8,             # read p, d and the inner solve's last direction; write p
@@ -64,7 +65,7 @@ def level_cells(cls, n_cells, n):
     return n_cells * (int(digits) / n) ** 3
 
 
-CLASSES = ("presmooth16", "preupd16", "postsmooth16", "apply16", "update", "xupdate", "resid64", "ir",
+CLASSES = ("presmooth16", "preupd16", "postsmooth16", "apply16", "update", "rprobe", "xupdate", "resid64", "ir",
            "coarse", "force", "div", "correct", "presmooth8", "postsmooth8", "presmooth4",
            "postsmooth4", "presmooth2", "postsmooth2", "restrict2", "finalize")
 

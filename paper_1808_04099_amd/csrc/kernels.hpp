@@ -98,7 +98,8 @@ struct UpdateArgs {     // x += alpha p; r -= alpha q; <r, r>_V
   const Scalars* sc;
   double* part;
   int x_zero;           // x starts at zero (not read)
-  int part_sel;         // 0: x and r; 1: r and <r, r> only; 2: x only
+  int part_sel;         // 0: x and r; 1: r and <r, r> only; 2: x only; 3: <r', r'> of the
+                        // updated r' only (r not written)
 };
 
 template <typename TO>

@@ -15,7 +15,7 @@ namespace {
 
 // x += alpha p; r -= alpha q; partial <r, r>_V.  One workgroup per cube.  SEL splits the two
 // updates (1: r and <r, r> only, 2: x only; 0: both), so that the x update can run beside the
-// next V-cycle.
+// next V-cycle; 3: <r - alpha q, r - alpha q>_V only, r left as it is (a convergence probe).
 template <typename T, int SEL>
 __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   __shared__ double red[8];
@@ -23,13 +23,13 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   const T al = T(a.sc->alpha);
   double rr = 0.0;
   const size_t base = (size_t)c * a.n3;
-  constexpr bool do_x = SEL != 1, do_r = SEL != 2;
+  constexpr bool do_x = SEL == 0 || SEL == 2, do_r = SEL != 2;
   for (int e = threadIdx.x; e < a.n3; e += WG) {
     const size_t g = base + e;
     if (do_x) st_nt(a.x + g, (a.x_zero ? T(0) : ld_nt(a.x + g)) + al * ld_nt(a.p + g));
     if (do_r) {
       const T rv = ld_nt(a.r + g) - al * ld_nt(a.q + g);
-      st_nt(a.r + g, rv);
+      if (SEL != 3) st_nt(a.r + g, rv);
       rr += double(rv) * double(rv);
     }
   }
@@ -748,6 +748,8 @@ hipError_t launch_update(const UpdateArgs<T>& a, hipStream_t s) {
     hipLaunchKernelGGL((k_update<T, 1>), dim3(a.n_cubes), dim3(WG), 0, s, a);
   else if (a.part_sel == 2)
     hipLaunchKernelGGL((k_update<T, 2>), dim3(a.n_cubes), dim3(WG), 0, s, a);
+  else if (a.part_sel == 3)
+    hipLaunchKernelGGL((k_update<T, 3>), dim3(a.n_cubes), dim3(WG), 0, s, a);
   else
     hipLaunchKernelGGL((k_update<T, 0>), dim3(a.n_cubes), dim3(WG), 0, s, a);
   return hipGetLastError();

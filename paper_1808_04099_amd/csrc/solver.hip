@@ -47,7 +47,7 @@ const char* const kTimerNames[] = {"presmooth16", "presmooth8", "presmooth4", "p
                                    "apply4", "apply2", "update", "resid64", "ir", "coarse",
                                    "finalize", "force", "div", "correct", "adj_gp", "adj_rhs",
                                    "export", "xupdate", "momentum", "momentum_start", "ib", "codec",
-                                   "preupd16", "preupd8", "preupd4", "preupd2", nullptr};
+                                   "preupd16", "preupd8", "preupd4", "preupd2", "rprobe", nullptr};
 
 int level_index(int NL) { return NL == 16 ? 0 : NL == 8 ? 1 : NL == 4 ? 2 : 3; }
 
@@ -477,10 +477,12 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
   // last iteration, or without a per-cube level to smooth (nlev < 2), it runs on its own.
   // A fused launch whose check ends the solve does its pre-smoothing for nothing, so when the
   // residual's last reduction factor predicts convergence at the next check (with checks every
-  // iteration), that update runs on its own instead.
+  // iteration), a probe computes that check's <r, r> alone, leaving r as it is (an ended solve
+  // never reads r again); if the solve goes on, the fused launch still applies the update and
+  // skips the check (probed).  After the last allowed iteration the probe also serves.
   const bool fuse = P->nlev >= 2;
   UpdateArgs<T> ur{};
-  bool r_pending = false;
+  bool r_pending = false, probed = false;
   double rr_a = -1.0, rr_b = -1.0;  // the last two checked <r, r> (rr_b the latest)
   // <r, r> of the update of iteration it (partials: nrr), and the convergence checks every
   // check_every iterations and at the last one
@@ -508,10 +510,14 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     }
     return BCM_OK;
   };
-  // the pending r update on its own (per-cube partials)
-  auto update_alone = [&](int it, bool& stop) -> int {
-    r_pending = false;
-    HIPCHK(timed(P, cls_of("update", 0), s, [&] { return launch_update<T>(ur, s); }), "k_update");
+  // the pending r update on its own (probe: only its <r, r>), with per-cube partials
+  auto update_alone = [&](int it, bool probe, bool& stop) -> int {
+    UpdateArgs<T> a = ur;
+    a.part_sel = probe ? 3 : 1;
+    r_pending = probe;
+    probed = probe;
+    HIPCHK(timed(P, cls_of(probe ? "rprobe" : "update", 0), s, [&] { return launch_update<T>(a, s); }),
+           "k_update");
     return check(it, P->nc, stop);
   };
   for (int it = 0; it < max_iter; ++it) {
@@ -521,8 +527,11 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
         rr_b * (rr_b / rr_a) <= 3.0 * thr)
       alone = true;  // predicted to converge at this check
     if (alone) {
-      if (const int st = update_alone(it - 1, stop)) return finish(st);
-      if (stop) break;
+      if (const int st = update_alone(it - 1, fuse, stop)) return finish(st);
+      if (stop) {  // an ended solve does not need the probed update
+        r_pending = false;
+        break;
+      }
     }
     int st = vcycle<T>(P, (flex && it > 0) ? q : nullptr, s,
                        [&](CoarseMGArgs<T>* carrier) { return start_x(true, carrier); },
@@ -530,6 +539,10 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
                        [&](bool& stop_) -> int {
                          if (!r_pending) return BCM_OK;
                          r_pending = false;
+                         if (probed) {  // checked already
+                           probed = false;
+                           return BCM_OK;
+                         }
                          return check(it - 1, nparts, stop_);
                        },
                        stop);
@@ -553,9 +566,9 @@ int krylov(bcm_plan* P, T* x, bool x_zero, double thr, int max_iter, double hist
     ux.part_sel = 2;
     pending = true;
   }
-  if (r_pending) {  // the last iteration's r update
+  if (r_pending) {  // the last iteration's check (r itself is not needed any more)
     bool stop = false;
-    if (const int st = update_alone(max_iter - 1, stop)) return finish(st);
+    if (const int st = update_alone(max_iter - 1, true, stop)) return finish(st);
   }
   return finish(BCM_OK);
 }

@@ -108,30 +108,32 @@ def test_sampled_kernel_timing(precision):
 
 def test_r_update_rides_in_the_next_first_presmoother():
     """The r update of each Krylov iteration is applied by the first pre-smoother of the next
-    V-cycle (timer class preupd8), after which the convergence check runs, except where the
-    last reduction factor predicts convergence at that check (then it runs on its own, and a
-    plain pre-smoother follows if the solve goes on): every update is one or the other.  A solve
-    stopped by max_iter runs its last update on its own."""
+    V-cycle (timer class preupd8), after which the convergence check runs.  Where the last
+    reduction factor predicts convergence at that check, a probe (rprobe) computes the check's
+    <r, r> first without writing r, and the fused launch follows only if the solve goes on (it
+    then skips the check).  So every iteration is checked once, there is no separate r update,
+    and the plain pre-smoother runs only in the first V-cycle.  After the last allowed
+    iteration the probe does the final check."""
     m, b = _problem()
     plan = plan_for(m, "fp64", tol=1e-10)
     counts = {}
-    for cls in ("preupd8", "update", "presmooth8"):
+    for cls in ("preupd8", "rprobe", "update", "presmooth8"):
         plan.timing_enable(cls)
         p, rep = plan.poisson_solve(dev(b))
         counts[cls] = plan.timing_read()[0]
         plan.timing_enable(None)
         assert rep.status == OK
     log(f"  converged: {counts}, n_inner {rep.n_inner}")
-    assert counts["preupd8"] + counts["update"] == rep.n_inner
-    assert counts["preupd8"] >= rep.n_inner - 3 and counts["update"] >= 1
-    # the first V-cycle's, and one after each update on its own that did not end the solve
-    assert counts["presmooth8"] in (counts["update"], counts["update"] + 1)
+    assert counts["update"] == 0 and counts["presmooth8"] == 1 and counts["rprobe"] >= 1
+    assert rep.n_inner in (counts["preupd8"], counts["preupd8"] + 1)
     _check_report(m, b, host(p), rep)
     plan = plan_for(m, "fp64", max_iter=3, max_outer=1)
-    plan.timing_enable("update")
-    p, rep = plan.poisson_solve(dev(b))
-    n_alone = plan.timing_read()[0]
-    plan.timing_enable(None)
-    log(f"  max_iter 3: status {rep.status}, {n_alone} separate r update(s)")
-    assert rep.status == NOT_CONVERGED and rep.n_inner == 3 and n_alone == 1
+    for cls in ("rprobe", "update"):
+        plan.timing_enable(cls)
+        p, rep = plan.poisson_solve(dev(b))
+        counts[cls] = plan.timing_read()[0]
+        plan.timing_enable(None)
+    log(f"  max_iter 3: status {rep.status}, {counts['rprobe']} probe(s), {counts['update']} update(s)")
+    assert rep.status == NOT_CONVERGED and rep.n_inner == 3
+    assert counts["rprobe"] == 1 and counts["update"] == 0
     _check_report(m, b, host(p), rep)
