@@ -174,6 +174,46 @@ __device__ __forceinline__ void export_col(T* xf, int c, const T (&x)[NL], int i
   base[5 * N2 + j * NL + i] = x[NL - 1];
 }
 
+// The same slabs written in two steps through LDS (16^3, one cube per workgroup).  The lanes on
+// an x or y face hold a face row along z in registers, which export_col stores one value per
+// instruction (16 instructions per face, a few lanes each).  Here those lanes put the row into
+// LDS with 16-byte writes (rows of XSP words, 16-byte aligned), and after a barrier every lane
+// reads one value of each of the four slabs and stores it, one coalesced line per wavefront.
+// The z slabs are stored directly (every lane holds one value of each).
+constexpr int XSP = 20;
+template <typename T>
+__device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[16], int i, int j) {
+  constexpr int N2 = 256;
+  auto put = [&](int f, int t1) {
+    T* row = xs + (f * 16 + t1) * XSP;
+#pragma unroll
+    for (int k = 0; k < 16; k += 4) {
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(row + k) = make_float4(x[k], x[k + 1], x[k + 2], x[k + 3]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) row[k + q] = x[k + q];
+      }
+    }
+  };
+  if (i == 0) put(0, j);
+  if (i == 15) put(1, j);
+  if (j == 0) put(2, i);
+  if (j == 15) put(3, i);
+  T* base = xf + (size_t)c * Col<16>::F;
+  base[4 * N2 + j * 16 + i] = x[0];
+  base[5 * N2 + j * 16 + i] = x[15];
+}
+// After a barrier that follows export_xy_put: lane t stores slab entry t (t2 = t / 16,
+// t1 = t % 16) of faces 0..3.
+template <typename T>
+__device__ __forceinline__ void export_xy_flush(const T* xs, T* xf, int c, int t) {
+  T* base = xf + (size_t)c * Col<16>::F;
+  const int t1 = t & 15, t2 = t >> 4;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) base[f * 256 + t] = xs[(f * 16 + t1) * XSP + t2];
+}
+
 // 2x2 means of the face slabs on faces that border a coarser cube (see face_stride), from the
 // cube's values in the LDS tile; summed in the order (0,0), (1,0), (0,1), (1,1) of the two
 // tangential axes.  Lanes of each cube slot with l < (NL/2)^2 compute one mean per face.
@@ -451,6 +491,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
   __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
   __shared__ uint32_t cdesc[TRI && PF ? ProPF<NL>::NT : 1];
   __shared__ T rsum[POST ? 1 : C::CPB * C::H * C::N2];  // pre: residual summed over k pairs
+  // the x and y slabs of the halo-free tile's cube and of the FP32 post-smoother's go out
+  // through LDS (export_xy_put); the post-smoother stores them after its next barrier
+  constexpr bool XS = ZL || (POST && NL == 16 && !ML && sizeof(T) == 4);
+  __shared__ __align__(16) T xst[XS ? 4 * NL * XSP : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
   const LaneC<NL> L(t);
@@ -527,6 +571,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
   uint32_t sgn = 0;
   int u = blockIdx.x;
   int c = u < U ? unit_cube<NL>(a.g, u, L.s) : -1;
+  int cx = -1;  // post-smoother: the cube whose x and y slabs wait in xst
   if (TRI && PF && u < U) {
     for (int e = t; e < ProPF<NL>::NT; e += 256) cdesc[e] = coarse_desc<NL>(e);
     coarse_ent<NL>(a.nb27, a.g.n_cubes, u, entn);
@@ -606,6 +651,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
     if (POST || RFX || a.sweeps == 0) __syncthreads();
+    if (POST && XS && cx >= 0) export_xy_flush<T>(xst, a.xf_out, cx, t);
     if constexpr (RFX) {
       // the finer level's restriction lacked the cross-cube terms of its residual: for each
       // face the cell lies on (x, y, then z), -(1/8) of the sum of its 2x2 finer halo values
@@ -753,9 +799,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
           if (a.q_dot) zq += vol * double(x[k]) * double(q[k]);
         }
       }
-      export_col<NL, T>(a.xf_out, c, x, i, j);
+      if constexpr (XS)
+        export_xy_put<T>(xst, a.xf_out, c, x, i, j);
+      else
+        export_col<NL, T>(a.xf_out, c, x, i, j);
       if (ML) export_avg<NL, T, MetaRO, CT>(a.xf_out, c, tile, m, L);
     }
+    if (ZL && !a.bc) __syncthreads();
     if (!POST && a.bc) {
       // residual with the halo the sweeps used (zero across cube faces), summed over the 2x2x2
       // children of each coarse cell; the face correction adds the cross-cube terms
@@ -783,9 +833,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
         if (c2 >= 0) a.bc[(size_t)c2 * C::H3 + le] = sum * T(0.125);
       }
     }
+    // (the next writes of xst come after the next cube's passes and their barriers)
+    if (ZL && c >= 0) export_xy_flush<T>(xst, a.xf_out, c, t);
     if (ML) __syncthreads();  // the means read the tile the next cube overwrites
+    if (POST && XS) cx = c;
     u = un;
     c = cn;
+  }
+  if (POST && XS && cx >= 0) {
+    __syncthreads();
+    export_xy_flush<T>(xst, a.xf_out, cx, t);
   }
   if (dots) {
     const double t0 = block_sum(zr, red);
