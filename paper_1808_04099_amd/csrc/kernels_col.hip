@@ -491,9 +491,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
   __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
   __shared__ uint32_t cdesc[TRI && PF ? ProPF<NL>::NT : 1];
   __shared__ T rsum[POST ? 1 : C::CPB * C::H * C::N2];  // pre: residual summed over k pairs
-  // the x and y slabs of the halo-free tile's cube and of the FP32 post-smoother's go out
-  // through LDS (export_xy_put); the post-smoother stores them after its next barrier
-  constexpr bool XS = ZL || (POST && NL == 16 && !ML && sizeof(T) == 4);
+  // the x and y slabs of the halo-free tile's cube and of the FP32 16^3 smoothers go out
+  // through LDS (export_xy_put), stored after the next barrier: the restriction's (halo-free
+  // tile), the one that ends the cube (multi-level meshes), else the next cube's first
+  constexpr bool XS = ZL || (NL == 16 && sizeof(T) == 4);
   __shared__ __align__(16) T xst[XS ? 4 * NL * XSP : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
@@ -651,7 +652,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
     if (POST || RFX || a.sweeps == 0) __syncthreads();
-    if (POST && XS && cx >= 0) export_xy_flush<T>(xst, a.xf_out, cx, t);
+    if (POST && XS && !ML && cx >= 0) export_xy_flush<T>(xst, a.xf_out, cx, t);
     if constexpr (RFX) {
       // the finer level's restriction lacked the cross-cube terms of its residual: for each
       // face the cell lies on (x, y, then z), -(1/8) of the sum of its 2x2 finer halo values
@@ -805,7 +806,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
         export_col<NL, T>(a.xf_out, c, x, i, j);
       if (ML) export_avg<NL, T, MetaRO, CT>(a.xf_out, c, tile, m, L);
     }
-    if (ZL && !a.bc) __syncthreads();
+    if (ZL && !a.bc) __syncthreads();  // (a level without a coarser one)
     if (!POST && a.bc) {
       // residual with the halo the sweeps used (zero across cube faces), summed over the 2x2x2
       // children of each coarse cell; the face correction adds the cross-cube terms
@@ -836,11 +837,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
     // (the next writes of xst come after the next cube's passes and their barriers)
     if (ZL && c >= 0) export_xy_flush<T>(xst, a.xf_out, c, t);
     if (ML) __syncthreads();  // the means read the tile the next cube overwrites
-    if (POST && XS) cx = c;
+    if (ML && XS && c >= 0) export_xy_flush<T>(xst, a.xf_out, c, t);
+    if (POST && XS && !ML) cx = c;
     u = un;
     c = cn;
   }
-  if (POST && XS && cx >= 0) {
+  if (POST && XS && !ML && cx >= 0) {
     __syncthreads();
     export_xy_flush<T>(xst, a.xf_out, cx, t);
   }
@@ -953,6 +955,9 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
   __shared__ T tile[C::CPB * C::TS];
+  // FP32 at 16^3: the x and y slabs of p go out through LDS (export_xy_put)
+  constexpr bool XS = NL == 16 && sizeof(T) == 4;
+  __shared__ __align__(16) T xst[XS ? 4 * NL * XSP : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
   const LaneC<NL> L(t);
@@ -1017,10 +1022,15 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
       }
     }
     if (c >= 0) {
-      export_col<NL, T>(a.pf_out, c, x, i, j);
+      if constexpr (XS)
+        export_xy_put<T>(xst, a.pf_out, c, x, i, j);
+      else
+        export_col<NL, T>(a.pf_out, c, x, i, j);
       if (ML) export_avg<NL, T>(a.pf_out, c, tile, m, L);
     }
     __syncthreads();
+    // (xst is written again after the next cube's first barrier)
+    if (XS && c >= 0) export_xy_flush<T>(xst, a.pf_out, c, t);
     u = un;
     c = cn;
   }
