@@ -174,20 +174,28 @@ __device__ __forceinline__ void export_col(T* xf, int c, const T (&x)[NL], int i
   base[5 * N2 + j * NL + i] = x[NL - 1];
 }
 
-// The same slabs written in two steps through LDS (16^3, one cube per workgroup).  The lanes on
-// an x or y face hold a face row along z in registers, which export_col stores one value per
-// instruction (16 instructions per face, a few lanes each).  Here those lanes put the row into
-// LDS with 16-byte writes (rows of XSP words, 16-byte aligned), and after a barrier every lane
-// reads one value of each of the four slabs and stores it, one coalesced line per wavefront.
-// The z slabs are stored directly (every lane holds one value of each).
-constexpr int XSP = 20;
-template <typename T>
-__device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[16], int i, int j) {
-  constexpr int N2 = 256;
+// The same slabs written in two steps through LDS (16^3 and 8^3).  The lanes on an x or y
+// face hold a face row along z in registers, which export_col stores one value per
+// instruction (NL instructions per face, a few lanes each).  Here those lanes put the row into
+// LDS with 16-byte writes (per cube slot, 4 faces of NL rows of NL + 4 words: 16-byte aligned,
+// and the reads below hit distinct banks at 8^3, two lanes per bank at 16^3), and after a
+// barrier every lane reads its entry of each of the four slabs and stores it, one coalesced
+// line per wavefront.  The z slabs are stored directly (every lane holds one value of each).
+template <int NL>
+struct XStage {
+  static constexpr int R = NL + 4;           // row pitch in words
+  static constexpr int S = 4 * NL * R;       // words per cube slot
+  static constexpr int TOTAL = Col<NL>::CPB * S;
+};
+template <int NL, typename T>
+__device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[NL], const LaneC<NL>& L) {
+  using X = XStage<NL>;
+  constexpr int N2 = Col<NL>::N2;
+  const int i = L.i, j = L.j;
   auto put = [&](int f, int t1) {
-    T* row = xs + (f * 16 + t1) * XSP;
+    T* row = xs + L.s * X::S + (f * NL + t1) * X::R;
 #pragma unroll
-    for (int k = 0; k < 16; k += 4) {
+    for (int k = 0; k < NL; k += 4) {
       if constexpr (sizeof(T) == 4) {
         *reinterpret_cast<float4*>(row + k) = make_float4(x[k], x[k + 1], x[k + 2], x[k + 3]);
       } else {
@@ -197,21 +205,23 @@ __device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[
     }
   };
   if (i == 0) put(0, j);
-  if (i == 15) put(1, j);
+  if (i == NL - 1) put(1, j);
   if (j == 0) put(2, i);
-  if (j == 15) put(3, i);
-  T* base = xf + (size_t)c * Col<16>::F;
-  base[4 * N2 + j * 16 + i] = x[0];
-  base[5 * N2 + j * 16 + i] = x[15];
+  if (j == NL - 1) put(3, i);
+  T* base = xf + (size_t)c * Col<NL>::F;
+  base[4 * N2 + j * NL + i] = x[0];
+  base[5 * N2 + j * NL + i] = x[NL - 1];
 }
-// After a barrier that follows export_xy_put: lane t stores slab entry t (t2 = t / 16,
-// t1 = t % 16) of faces 0..3.
-template <typename T>
-__device__ __forceinline__ void export_xy_flush(const T* xs, T* xf, int c, int t) {
-  T* base = xf + (size_t)c * Col<16>::F;
-  const int t1 = t & 15, t2 = t >> 4;
+// After a barrier that follows export_xy_put: lane l of a cube slot stores slab entry l
+// (t2 = l / NL, t1 = l % NL) of faces 0..3.
+template <int NL, typename T>
+__device__ __forceinline__ void export_xy_flush(const T* xs, T* xf, int c, const LaneC<NL>& L) {
+  using X = XStage<NL>;
+  constexpr int N2 = Col<NL>::N2;
+  T* base = xf + (size_t)c * Col<NL>::F;
+  const int t1 = L.l % NL, t2 = L.l / NL;
 #pragma unroll
-  for (int f = 0; f < 4; ++f) base[f * 256 + t] = xs[(f * 16 + t1) * XSP + t2];
+  for (int f = 0; f < 4; ++f) base[f * N2 + L.l] = xs[L.s * X::S + (f * NL + t1) * X::R + t2];
 }
 
 // 2x2 means of the face slabs on faces that border a coarser cube (see face_stride), from the
@@ -491,11 +501,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
   __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
   __shared__ uint32_t cdesc[TRI && PF ? ProPF<NL>::NT : 1];
   __shared__ T rsum[POST ? 1 : C::CPB * C::H * C::N2];  // pre: residual summed over k pairs
-  // the x and y slabs of the halo-free tile's cube and of the FP32 16^3 smoothers go out
-  // through LDS (export_xy_put), stored after the next barrier: the restriction's (halo-free
-  // tile), the one that ends the cube (multi-level meshes), else the next cube's first
-  constexpr bool XS = ZL || (NL == 16 && sizeof(T) == 4);
-  __shared__ __align__(16) T xst[XS ? 4 * NL * XSP : 1];
+  // the x and y slabs of the halo-free tile's cube and of the FP32 16^3 and 8^3 smoothers go
+  // out through LDS (export_xy_put), stored after the next barrier: the restriction's
+  // (pre-smoothers of single-level meshes), the one that ends the cube (multi-level meshes),
+  // else the next unit's first (not the trilinear 8^3 post-smoother, which would spill)
+  constexpr bool XS = ZL || ((NL == 16 || (NL == 8 && (ML || !POST))) && sizeof(T) == 4);
+  constexpr bool XPRE = XS && !POST && !ML;  // stored after the restriction's barrier
+  __shared__ __align__(16) T xst[XS ? XStage<NL>::TOTAL : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
   const LaneC<NL> L(t);
@@ -652,7 +664,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
     const int un = u + G;
     const int cn = un < U ? unit_cube<NL>(a.g, un, L.s) : -1;
     if (POST || RFX || a.sweeps == 0) __syncthreads();
-    if (POST && XS && !ML && cx >= 0) export_xy_flush<T>(xst, a.xf_out, cx, t);
+    if (POST && XS && !ML && cx >= 0) export_xy_flush<NL, T>(xst, a.xf_out, cx, L);
     if constexpr (RFX) {
       // the finer level's restriction lacked the cross-cube terms of its residual: for each
       // face the cell lies on (x, y, then z), -(1/8) of the sum of its 2x2 finer halo values
@@ -801,12 +813,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
         }
       }
       if constexpr (XS)
-        export_xy_put<T>(xst, a.xf_out, c, x, i, j);
+        export_xy_put<NL, T>(xst, a.xf_out, c, x, L);
       else
         export_col<NL, T>(a.xf_out, c, x, i, j);
       if (ML) export_avg<NL, T, MetaRO, CT>(a.xf_out, c, tile, m, L);
     }
-    if (ZL && !a.bc) __syncthreads();  // (a level without a coarser one)
+    if (XPRE && !a.bc) __syncthreads();  // (a level without a coarser one)
     if (!POST && a.bc) {
       // residual with the halo the sweeps used (zero across cube faces), summed over the 2x2x2
       // children of each coarse cell; the face correction adds the cross-cube terms
@@ -835,16 +847,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
       }
     }
     // (the next writes of xst come after the next cube's passes and their barriers)
-    if (ZL && c >= 0) export_xy_flush<T>(xst, a.xf_out, c, t);
+    if (XPRE && c >= 0) export_xy_flush<NL, T>(xst, a.xf_out, c, L);
     if (ML) __syncthreads();  // the means read the tile the next cube overwrites
-    if (ML && XS && c >= 0) export_xy_flush<T>(xst, a.xf_out, c, t);
+    if (ML && XS && c >= 0) export_xy_flush<NL, T>(xst, a.xf_out, c, L);
     if (POST && XS && !ML) cx = c;
     u = un;
     c = cn;
   }
-  if (POST && XS && !ML && cx >= 0) {
+  if (POST && XS && !ML) {
     __syncthreads();
-    export_xy_flush<T>(xst, a.xf_out, cx, t);
+    if (cx >= 0) export_xy_flush<NL, T>(xst, a.xf_out, cx, L);
   }
   if (dots) {
     const double t0 = block_sum(zr, red);
@@ -957,7 +969,7 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   __shared__ T tile[C::CPB * C::TS];
   // FP32 at 16^3: the x and y slabs of p go out through LDS (export_xy_put)
   constexpr bool XS = NL == 16 && sizeof(T) == 4;
-  __shared__ __align__(16) T xst[XS ? 4 * NL * XSP : 1];
+  __shared__ __align__(16) T xst[XS ? XStage<NL>::TOTAL : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
   const LaneC<NL> L(t);
@@ -1023,14 +1035,14 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
     }
     if (c >= 0) {
       if constexpr (XS)
-        export_xy_put<T>(xst, a.pf_out, c, x, i, j);
+        export_xy_put<NL, T>(xst, a.pf_out, c, x, L);
       else
         export_col<NL, T>(a.pf_out, c, x, i, j);
       if (ML) export_avg<NL, T>(a.pf_out, c, tile, m, L);
     }
     __syncthreads();
     // (xst is written again after the next cube's first barrier)
-    if (XS && c >= 0) export_xy_flush<T>(xst, a.pf_out, c, t);
+    if (XS && c >= 0) export_xy_flush<NL, T>(xst, a.pf_out, c, L);
     u = un;
     c = cn;
   }
