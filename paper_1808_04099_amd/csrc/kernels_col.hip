@@ -187,7 +187,8 @@ struct XStage {
   static constexpr int S = 4 * NL * R;       // words per cube slot
   static constexpr int TOTAL = Col<NL>::CPB * S;
 };
-template <int NL, typename T>
+// NZ: no z slabs (the consumer reads the z neighbours from the field itself).
+template <int NL, typename T, bool NZ = false>
 __device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[NL], const LaneC<NL>& L) {
   using X = XStage<NL>;
   constexpr int N2 = Col<NL>::N2;
@@ -208,6 +209,7 @@ __device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[
   if (i == NL - 1) put(1, j);
   if (j == 0) put(2, i);
   if (j == NL - 1) put(3, i);
+  if (NZ) return;
   T* base = xf + (size_t)c * Col<NL>::F;
   base[4 * N2 + j * NL + i] = x[0];
   base[5 * N2 + j * NL + i] = x[NL - 1];
@@ -507,6 +509,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
   // else the next unit's first (not the trilinear 8^3 post-smoother, which would spill)
   constexpr bool XS = ZL || ((NL == 16 || (NL == 8 && (ML || !POST))) && sizeof(T) == 4);
   constexpr bool XPRE = XS && !POST && !ML;  // stored after the restriction's barrier
+  // the FP32 16^3 post-smoother of a single-level mesh feeds only apply, which reads the z
+  // neighbours of z from z itself: no z slabs
+  constexpr bool NZ = POST && !ML && NL == 16 && sizeof(T) == 4;
   __shared__ __align__(16) T xst[XS ? XStage<NL>::TOTAL : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
@@ -813,7 +818,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
         }
       }
       if constexpr (XS)
-        export_xy_put<NL, T>(xst, a.xf_out, c, x, L);
+        export_xy_put<NL, T, NZ>(xst, a.xf_out, c, x, L);
       else
         export_col<NL, T>(a.xf_out, c, x, i, j);
       if (ML) export_avg<NL, T, MetaRO, CT>(a.xf_out, c, tile, m, L);
@@ -969,6 +974,10 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   __shared__ T tile[C::CPB * C::TS];
   // FP32 at 16^3: the x and y slabs of p go out through LDS (export_xy_put)
   constexpr bool XS = NL == 16 && sizeof(T) == 4;
+  // FP32 at 16^3 on a single-level mesh: the z neighbours of z are read from z (which this
+  // kernel does not write; whole lines of the neighbours' end planes); its post-smoother
+  // exports no z slabs
+  constexpr bool ZD = XS && !ML;
   __shared__ __align__(16) T xst[XS ? XStage<NL>::TOTAL : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
@@ -990,8 +999,16 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       kinds[f] = S.kind[f];
-      rz[f] = a.zf[S.fine[f]];
       rp[f] = a.first ? T(0) : a.pf_in[S.fine[f]];
+      if (!ZD || f < 4) {
+        rz[f] = a.zf[S.fine[f]];
+      } else {
+        // the neighbour's cell next to the face at (i, j): (i, j, NL-1) below, (i, j, 0)
+        // above; across a domain boundary a cell of this cube (the value is not used)
+        MetaRO& mm = meta_ro(a.g.meta, cc);
+        const int nb = S.kind[f] == FK_SAME ? mm.nbr[f][0] : cc;
+        rz[f] = a.z[(size_t)nb * C::N3 + (f == 4 ? (NL - 1) * C::N2 : 0) + j * NL + i];
+      }
     }
   };
   int u = blockIdx.x;
