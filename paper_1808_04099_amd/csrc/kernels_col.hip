@@ -503,15 +503,15 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
   __shared__ uint32_t cent[TRI && PF ? ProPF<NL>::NN : 1];
   __shared__ uint32_t cdesc[TRI && PF ? ProPF<NL>::NT : 1];
   __shared__ T rsum[POST ? 1 : C::CPB * C::H * C::N2];  // pre: residual summed over k pairs
-  // the x and y slabs of the halo-free tile's cube and of the FP32 16^3 and 8^3 smoothers go
-  // out through LDS (export_xy_put), stored after the next barrier: the restriction's
+  // the x and y slabs of the 16^3 smoothers and of the FP32 8^3 ones go out through LDS
+  // (export_xy_put), stored after the next barrier: the restriction's
   // (pre-smoothers of single-level meshes), the one that ends the cube (multi-level meshes),
   // else the next unit's first (not the trilinear 8^3 post-smoother, which would spill)
-  constexpr bool XS = ZL || ((NL == 16 || (NL == 8 && (ML || !POST))) && sizeof(T) == 4);
+  constexpr bool XS = ZL || NL == 16 || (NL == 8 && (ML || !POST) && sizeof(T) == 4);
   constexpr bool XPRE = XS && !POST && !ML;  // stored after the restriction's barrier
-  // the FP32 16^3 post-smoother of a single-level mesh feeds only apply, which reads the z
+  // the 16^3 post-smoother of a single-level mesh feeds only apply, which reads the z
   // neighbours of z from z itself: no z slabs
-  constexpr bool NZ = POST && !ML && NL == 16 && sizeof(T) == 4;
+  constexpr bool NZ = POST && !ML && NL == 16;
   __shared__ __align__(16) T xst[XS ? XStage<NL>::TOTAL : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
@@ -972,11 +972,11 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   using C = Col<NL>;
   constexpr bool PF = sizeof(T) == 4 || NL < 16;
   __shared__ T tile[C::CPB * C::TS];
-  // FP32 at 16^3: the x and y slabs of p go out through LDS (export_xy_put)
-  constexpr bool XS = NL == 16 && sizeof(T) == 4;
-  // FP32 at 16^3 on a single-level mesh: the z neighbours of z are read from z (which this
-  // kernel does not write; whole lines of the neighbours' end planes); its post-smoother
-  // exports no z slabs
+  // at 16^3: the x and y slabs of p go out through LDS (export_xy_put)
+  constexpr bool XS = NL == 16;
+  // at 16^3 on a single-level mesh: the z neighbours of z are read from z (which this kernel
+  // does not write; whole lines of the neighbours' end planes); its post-smoother exports no
+  // z slabs
   constexpr bool ZD = XS && !ML;
   __shared__ __align__(16) T xst[XS ? XStage<NL>::TOTAL : 1];
   __shared__ double red[8];
