@@ -3,11 +3,14 @@
 // 7-point diffusion, for explicit Euler / Adams-Bashforth steps and the Jacobi iterations of
 // the Crank-Nicolson system.
 //
-// QUICK reaches two cells upwind, so every velocity field with a halo carries a two-layer face
-// buffer: per cube and component, faces f = 0..5 (-x, +x, -y, +y, -z, +z), layers L = 0
-// (boundary layer) and 1 (next inside), NL^2 values each as [t2][t1] (tangential axes in
-// increasing order).  Producers export it (k_mom_export for a caller's field, the iteration
-// kernels for their own output); consumers gather the neighbours' layers.  On a domain face
+// QUICK reaches two cells upwind, so the halo is two layers deep.  The y and z layers of a
+// neighbour are rows and planes of its cube (whole lines), read from the field itself, which
+// no pass writes while it is read (the iteration alternates between two arrays).  The x
+// layers (one value per row) go through a face buffer: per cube and component, faces f = 0..5
+// (-x, +x, -y, +y, -z, +z; only 0 and 1 are written), layers L = 0 (boundary layer) and 1
+// (next inside), NL^2 values each as [t2][t1] (tangential axes in increasing order).
+// Producers export it (k_mom_export for a caller's field, the iteration kernels for their own
+// output); consumers gather the neighbours' layers.  On a domain face
 // the two ghost layers mirror the cube's own two boundary layers: Dirichlet value g gives
 // 2 g - v, zero gradient gives v (inflow: every component Dirichlet, the normal one U_in into
 // the domain; slip: normal component Dirichlet 0, tangential zero gradient; open: zero
@@ -48,7 +51,7 @@ __device__ __forceinline__ Affine mom_rule(int kd, int f, int comp, double U_in)
   return {1.0, 0.0};  // a neighbour, an open face, or a tangential component on a slip wall
 }
 
-// Write the lane's share of the two-layer faces of one component from its column x[0..NL-1].
+// Write the lane's share of the two-layer x faces of one component from its column x[0..NL-1].
 template <int NL, typename TF>
 __device__ __forceinline__ void mom_export_col(TF* mf, int c, const double (&x)[NL], int i, int j) {
   using M = Mom<NL>;
@@ -61,14 +64,6 @@ __device__ __forceinline__ void mom_export_col(TF* mf, int c, const double (&x)[
     if (i == NL - 1 - L)
 #pragma unroll
       for (int k = 0; k < NL; ++k) base[M::fidx(1, L, j, k)] = TF(x[k]);
-    if (j == L)
-#pragma unroll
-      for (int k = 0; k < NL; ++k) base[M::fidx(2, L, i, k)] = TF(x[k]);
-    if (j == NL - 1 - L)
-#pragma unroll
-      for (int k = 0; k < NL; ++k) base[M::fidx(3, L, i, k)] = TF(x[k]);
-    base[M::fidx(4, L, i, j)] = TF(x[L]);
-    base[M::fidx(5, L, i, j)] = TF(x[NL - 1 - L]);
   }
 }
 
@@ -107,32 +102,44 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
     const CubeMeta& m = a.meta[ce];
     const double ih = 1.0 / m.h, ih2 = ih * ih;
     const size_t cb = (size_t)ce * M::N3 + l;
-    // Face sources of this lane: element offsets (per component array) of the two layers it
-    // reads across the -z / +z faces at (i, j), and, for the ring lanes (rows j = 0..3 of the
-    // slot, face f = j), across face f at tangential position i (plane offset k * NL added in
-    // the loop); each with the affine rule per component.
+    // Halo sources of this lane, each with the affine rule per component: the two layers
+    // across the -z / +z faces at (i, j), element offsets into the fields (the neighbour's
+    // planes NL-1, NL-2 / 0, 1; on a domain face the cube's own planes 0, 1 / NL-1, NL-2); and,
+    // for the ring lanes (rows j = 0..3 of the slot, face f = j), the two layers across face f
+    // at tangential position i, per plane k at ro + k * rs: for the x faces offsets into the
+    // face buffers (rs = NL), for the y faces into the fields (the neighbour's rows NL-1, NL-2
+    // / 0, 1, or the cube's own rows; rs = N2).
     size_t zo[2][2], ro[2] = {0, 0};
     Affine zr[2][4], rr[4];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int f = 4 + side, kd = m.kind[f];
       const bool nbr = kd == FK_SAME;
-      const size_t base = nbr ? (size_t)m.nbr[f][0] * M::FS : (size_t)ce * M::FS;
-      const int fs = nbr ? f ^ 1 : f;
+      const size_t cube = nbr ? (size_t)m.nbr[f][0] : (size_t)ce;
 #pragma unroll
-      for (int L = 0; L < 2; ++L) zo[side][L] = base + M::fidx(fs, L, i, j);
+      for (int L = 0; L < 2; ++L) {
+        // the layer L planes away from the shared face: the neighbour's far side, or this
+        // cube's own near side mirrored
+        const int plane = (side == 0) == nbr ? NL - 1 - L : L;
+        zo[side][L] = cube * M::N3 + (size_t)plane * M::N2 + j * NL + i;
+      }
 #pragma unroll
       for (int comp = 0; comp < 3; ++comp) zr[side][comp] = nbr ? Affine{1.0, 0.0} : mom_rule(kd, f, comp, a.U_in);
     }
     const bool ring = j < 4;
     const int rf = j & 3, rd = rf >> 1, rside = rf & 1;
+    const bool ry = rf >= 2;  // a y face: rows of the fields
+    const size_t rs = ry ? M::N2 : NL;
     {
       const int kd = m.kind[rf];
       const bool nbr = kd == FK_SAME;
-      const size_t base = nbr ? (size_t)m.nbr[rf][0] * M::FS : (size_t)ce * M::FS;
+      const size_t cube = nbr ? (size_t)m.nbr[rf][0] : (size_t)ce;
       const int fs = nbr ? rf ^ 1 : rf;
 #pragma unroll
-      for (int L = 0; L < 2; ++L) ro[L] = base + M::fidx(fs, L, i, 0);
+      for (int L = 0; L < 2; ++L) {
+        const int row = (rside == 0) == nbr ? NL - 1 - L : L;
+        ro[L] = ry ? cube * M::N3 + (size_t)row * NL + i : cube * M::FS + M::fidx(fs, L, i, 0);
+      }
 #pragma unroll
       for (int comp = 0; comp < 3; ++comp) rr[comp] = nbr ? Affine{1.0, 0.0} : mom_rule(kd, rf, comp, a.U_in);
     }
@@ -143,15 +150,15 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
     for (int comp = 0; comp < 3; ++comp) {
 #pragma unroll
       for (int L = 0; L < 2; ++L) {
-        gh[comp][L] = zr[1][comp].scale * double(a.vf[comp][zo[1][L]]) + zr[1][comp].shift;
-        wv[comp][1 - L] = zr[0][comp].scale * double(a.vf[comp][zo[0][L]]) + zr[0][comp].shift;
+        gh[comp][L] = zr[1][comp].scale * double(a.v[comp][zo[1][L]]) + zr[1][comp].shift;
+        wv[comp][1 - L] = zr[0][comp].scale * double(a.v[comp][zo[0][L]]) + zr[0][comp].shift;
       }
       wv[comp][2] = double(a.v[comp][cb]);
       wv[comp][3] = double(a.v[comp][cb + M::N2]);
       wv[comp][4] = double(a.v[comp][cb + 2 * M::N2]);
     }
-    const double azh = zr[1][2].scale * double(a.af[2][zo[1][0]]) + zr[1][2].shift;
-    za[0] = zr[0][2].scale * double(a.af[2][zo[0][0]]) + zr[0][2].shift;
+    const double azh = zr[1][2].scale * double(a.a[2][zo[1][0]]) + zr[1][2].shift;
+    za[0] = zr[0][2].scale * double(a.a[2][zo[0][0]]) + zr[0][2].shift;
     za[1] = double(a.a[2][cb]);
     za[2] = double(a.a[2][cb + M::N2]);
     const int rpos0 = rside ? NL + 2 : 1, rpos1 = rside ? NL + 3 : 0;  // ring index along rd
@@ -172,16 +179,12 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
         const double o = po[comp];
         a.out[comp][gp] = TF(o);
         if (a.hout[comp]) a.hout[comp][gp] = TF(ph[comp]);
-        if (a.outf[comp]) {  // two-layer faces of the output, cell by cell
+        if (a.outf[comp]) {  // two-layer x faces of the output, cell by cell
           TF* fb = a.outf[comp] + (size_t)c * M::FS;
 #pragma unroll
           for (int L = 0; L < 2; ++L) {
             if (i == L) fb[M::fidx(0, L, j, kp)] = TF(o);
             if (i == NL - 1 - L) fb[M::fidx(1, L, j, kp)] = TF(o);
-            if (j == L) fb[M::fidx(2, L, i, kp)] = TF(o);
-            if (j == NL - 1 - L) fb[M::fidx(3, L, i, kp)] = TF(o);
-            if (kp == L) fb[M::fidx(4, L, i, j)] = TF(o);
-            if (kp == NL - 1 - L) fb[M::fidx(5, L, i, j)] = TF(o);
           }
         }
       }
@@ -198,13 +201,14 @@ __global__ __launch_bounds__(256, 2) void k_mom(MomArgs<TF> a) {
       }
       TF rgv[7];
       if (ring) {
-        const size_t ko = (size_t)k * NL;
+        const size_t ko = (size_t)k * rs;
 #pragma unroll
         for (int comp = 0; comp < 3; ++comp) {
-          rgv[2 * comp] = a.vf[comp][ro[0] + ko];
-          rgv[2 * comp + 1] = a.vf[comp][ro[1] + ko];
+          const TF* src = ry ? a.v[comp] : a.vf[comp];
+          rgv[2 * comp] = src[ro[0] + ko];
+          rgv[2 * comp + 1] = src[ro[1] + ko];
         }
-        rgv[6] = a.af[rd][ro[0] + ko];
+        rgv[6] = (ry ? a.a[rd] : a.af[rd])[ro[0] + ko];
       }
       if (k > 0) put(k - 1);
       // plane k into LDS: interior, then the rings
