@@ -254,7 +254,8 @@ struct MomArgs {
   // MOM_EXPLICIT  out = v + dt (c1 H(v) + c2 hprev)                 (v = a = u^n)
   // MOM_CN_START  rhs = v + dt/2 H(v); out = v + dt H(v); part: sum rhs^2   (v = a = u^n)
   // MOM_CN_ITER   r = rhs + dt/2 H(v) - v; out = v + r / diag; part: sum r^2 (v = iterate)
-  // every mode: hout = H(v) (optional), outf = two-layer faces of out (optional)
+  // every mode: hout = H(v) (optional), outf = two-layer x faces of out (optional); vf / af:
+  // the x faces of v / a (their y and z halos are read from v / a themselves)
   const CubeMeta* meta;
   int n_cubes;
   const TF* v[3];

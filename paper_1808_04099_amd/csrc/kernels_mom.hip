@@ -6,9 +6,9 @@
 // QUICK reaches two cells upwind, so the halo is two layers deep.  The y and z layers of a
 // neighbour are rows and planes of its cube (whole lines), read from the field itself, which
 // no pass writes while it is read (the iteration alternates between two arrays).  The x
-// layers (one value per row) go through a face buffer: per cube and component, faces f = 0..5
-// (-x, +x, -y, +y, -z, +z; only 0 and 1 are written), layers L = 0 (boundary layer) and 1
-// (next inside), NL^2 values each as [t2][t1] (tangential axes in increasing order).
+// layers (one value per row) go through a face buffer: per cube and component, faces f = 0, 1
+// (-x, +x), layers L = 0 (boundary layer) and 1 (next inside), NL^2 values each as [t2][t1]
+// (y, z).
 // Producers export it (k_mom_export for a caller's field, the iteration kernels for their own
 // output); consumers gather the neighbours' layers.  On a domain face
 // the two ghost layers mirror the cube's own two boundary layers: Dirichlet value g gives
@@ -34,7 +34,7 @@ struct Mom {
   static constexpr int CPB = NL >= 16 ? 1 : 256 / N2;
   static constexpr int W4 = NL + 4, P4 = W4 * W4;  // plane with a two-cell ring
   static constexpr int W2 = NL + 2, P2 = W2 * W2;  // plane with a one-cell ring
-  static constexpr int FS = 12 * N2;               // face-buffer values per cube and component
+  static constexpr int FS = 4 * N2;                // face-buffer values per cube and component
   __device__ static int fidx(int f, int L, int t1, int t2) { return (f * 2 + L) * N2 + t2 * NL + t1; }
 };
 

@@ -1316,7 +1316,7 @@ int bcm_plan_create(const bcm_mesh* mesh, const bcm_solver_opts* opts, bcm_plan*
   }
   P->momentum = !M.multilevel && M.n >= 4;
   if (P->momentum) {
-    const size_t mfs = size_t(12) * M.n * M.n * nc * Tf;
+    const size_t mfs = size_t(4) * M.n * M.n * nc * Tf;  // two x layers per face (kernels_mom.hip)
     for (int d = 0; d < 3; ++d) {
       P->o_mfa[d] = take(top, mfs);
       P->o_mfv[0][d] = take(top, mfs);
