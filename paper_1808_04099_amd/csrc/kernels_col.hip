@@ -187,9 +187,11 @@ struct XStage {
   static constexpr int S = 4 * NL * R;       // words per cube slot
   static constexpr int TOTAL = Col<NL>::CPB * S;
 };
-// NZ: no z slabs (the consumer reads the z neighbours from the field itself).
+// NZ: no z slabs (the consumer reads the z neighbours from the field itself); z0 / z1: store
+// the -z / +z slab.
 template <int NL, typename T, bool NZ = false>
-__device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[NL], const LaneC<NL>& L) {
+__device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[NL], const LaneC<NL>& L,
+                                              bool z0 = true, bool z1 = true) {
   using X = XStage<NL>;
   constexpr int N2 = Col<NL>::N2;
   const int i = L.i, j = L.j;
@@ -211,8 +213,8 @@ __device__ __forceinline__ void export_xy_put(T* xs, T* xf, int c, const T (&x)[
   if (j == NL - 1) put(3, i);
   if (NZ) return;
   T* base = xf + (size_t)c * Col<NL>::F;
-  base[4 * N2 + j * NL + i] = x[0];
-  base[5 * N2 + j * NL + i] = x[NL - 1];
+  if (z0) base[4 * N2 + j * NL + i] = x[0];
+  if (z1) base[5 * N2 + j * NL + i] = x[NL - 1];
 }
 // After a barrier that follows export_xy_put: lane l of a cube slot stores slab entry l
 // (t2 = l / NL, t1 = l % NL) of faces 0..3.
@@ -512,6 +514,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
   // the 16^3 post-smoother of a single-level mesh feeds only apply, which reads the z
   // neighbours of z from z itself: no z slabs
   constexpr bool NZ = POST && !ML && NL == 16;
+  // on a multi-level mesh its z slab is read across a face only by a finer neighbour (apply
+  // reads a same-level neighbour from z itself, a coarser one's 2x2 means): stored only there
+  constexpr bool MZ = POST && ML && NL == 16;
   __shared__ __align__(16) T xst[XS ? XStage<NL>::TOTAL : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
@@ -818,7 +823,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? (NL == 8 ? 4 : 3) : 2) void k
         }
       }
       if constexpr (XS)
-        export_xy_put<NL, T, NZ>(xst, a.xf_out, c, x, L);
+        export_xy_put<NL, T, NZ>(xst, a.xf_out, c, x, L, !MZ || kind_of(m, 4) == FK_FINER,
+                                 !MZ || kind_of(m, 5) == FK_FINER);
       else
         export_col<NL, T>(a.xf_out, c, x, i, j);
       if (ML) export_avg<NL, T, MetaRO, CT>(a.xf_out, c, tile, m, L);
@@ -974,10 +980,10 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
   __shared__ T tile[C::CPB * C::TS];
   // at 16^3: the x and y slabs of p go out through LDS (export_xy_put)
   constexpr bool XS = NL == 16;
-  // at 16^3 on a single-level mesh: the z neighbours of z are read from z (which this kernel
-  // does not write; whole lines of the neighbours' end planes); its post-smoother exports no
-  // z slabs
-  constexpr bool ZD = XS && !ML;
+  // at 16^3: the z neighbours of z of the same level are read from z (which this kernel does
+  // not write; whole lines of the neighbours' end planes), so the post-smoother stores z slabs
+  // only where a finer neighbour reads them
+  constexpr bool ZD = XS;
   __shared__ __align__(16) T xst[XS ? XStage<NL>::TOTAL : 1];
   __shared__ double red[8];
   const int t = threadIdx.x;
@@ -1000,7 +1006,7 @@ __global__ __launch_bounds__(256) void kc_apply(ApplyArgs<T> a) {
     for (int f = 0; f < 6; ++f) {
       kinds[f] = S.kind[f];
       rp[f] = a.first ? T(0) : a.pf_in[S.fine[f]];
-      if (!ZD || f < 4) {
+      if (!ZD || f < 4 || (ML && S.kind[f] != FK_SAME)) {
         rz[f] = a.zf[S.fine[f]];
       } else {
         // the neighbour's cell next to the face at (i, j): (i, j, NL-1) below, (i, j, 0)
